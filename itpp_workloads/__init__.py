@@ -1,0 +1,262 @@
+"""Seeded synthetic inputs for imaginary-time Pauli propagation (ITPP).
+
+This module only *describes* workloads: Hamiltonian terms as Pauli strings
+with real weights, the gate order of one Trotter step, step counts,
+observables and the seeded draws that pick model parameters.  It holds none
+of the method's arithmetic (no products of Pauli strings, no cosh/sinh, no
+truncation), so both the CPU oracle and the GPU library can take their inputs
+from here without sharing any computation.
+
+Conventions
+-----------
+* A Pauli string on ``n`` qubits is a Python ``str`` of length ``n`` over the
+  letters ``I X Y Z``; character ``j`` is qubit ``j``.
+* The transverse-field Ising chain of the paper's Eq. (TFIM) is
+  ``H = -J sum_i Z_i Z_{i+1} - h sum_i X_i``; periodic chains add the bond
+  ``(n-1, 0)``.  Terms are listed as all ZZ bonds ``(0,1), (1,2), ...`` then the
+  periodic bond if present, then ``X_0 .. X_{n-1}``.
+* A schedule is one Trotter step: a list of ``(term_index, multiplier)``.  The
+  gate for entry ``(k, m)`` has angle ``theta = alpha_k * m * dtau``.
+  First order (Algorithm 1): every term once with ``m = 1`` (ZZ layer then X
+  layer).  Second order (the Strang splitting of Sec. II.C): ZZ layer with
+  ``m = 1/2``, X layer with ``m = 1``, ZZ layer with ``m = 1/2``; the half
+  layers of consecutive steps are not merged.
+* The number of steps for a target inverse temperature ``beta`` is
+  ``ceil(beta/dtau - 1e-9)`` (Algorithm 1 takes the ceiling; the small offset
+  absorbs floating-point noise in ``beta/dtau``).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+PAULI_LETTERS = "IXYZ"
+
+
+def single_site(n: int, site: int, letter: str) -> str:
+    s = ["I"] * n
+    s[site] = letter
+    return "".join(s)
+
+
+def two_site(n: int, i: int, j: int, li: str, lj: str) -> str:
+    s = ["I"] * n
+    s[i] = li
+    s[j] = lj
+    return "".join(s)
+
+
+def tfim_terms(n: int, J: float, h: float, periodic: bool) -> Tuple[List[str], List[float], int]:
+    """Terms of H = -J sum Z_i Z_{i+1} - h sum X_i.
+
+    Returns ``(strings, alphas, n_zz)`` where the first ``n_zz`` terms are the
+    ZZ bonds and the rest are the ``n`` single-site X terms.
+    """
+    if n < 2:
+        raise ValueError("a chain needs at least two qubits")
+    strings: List[str] = []
+    alphas: List[float] = []
+    for i in range(n - 1):
+        strings.append(two_site(n, i, i + 1, "Z", "Z"))
+        alphas.append(-float(J))
+    if periodic and n > 2:
+        strings.append(two_site(n, n - 1, 0, "Z", "Z"))
+        alphas.append(-float(J))
+    n_zz = len(strings)
+    for i in range(n):
+        strings.append(single_site(n, i, "X"))
+        alphas.append(-float(h))
+    return strings, alphas, n_zz
+
+
+def tfim_schedule(n_zz: int, n_x: int, order: int) -> List[Tuple[int, float]]:
+    """Gate list of one Trotter step for the term layout of ``tfim_terms``."""
+    zz = list(range(n_zz))
+    xx = list(range(n_zz, n_zz + n_x))
+    if order == 1:
+        return [(k, 1.0) for k in zz] + [(k, 1.0) for k in xx]
+    if order == 2:
+        return [(k, 0.5) for k in zz] + [(k, 1.0) for k in xx] + [(k, 0.5) for k in zz]
+    raise ValueError("order must be 1 or 2")
+
+
+def n_steps_for(beta: float, dtau: float) -> int:
+    return int(math.ceil(beta / dtau - 1e-9))
+
+
+def draw_uniform(seed: int, lo: float, hi: float, size: Optional[int] = None):
+    rng = np.random.default_rng(seed)
+    v = rng.uniform(lo, hi, size=size)
+    return float(v) if size is None else v
+
+
+@dataclass
+class Workload:
+    """One ITPP run: Hamiltonian terms, one Trotter step's gates, step size,
+    number of steps, truncation threshold ``delta`` (keep ``|c| > delta``) and
+    term cap ``K``."""
+
+    name: str
+    n: int
+    strings: List[str]
+    alphas: List[float]
+    schedule: List[Tuple[int, float]]
+    dtau: float
+    n_steps: int
+    delta: float
+    K: int
+    precision: str = "f64"
+    observables: Dict[str, Tuple[List[str], List[float]]] = field(default_factory=dict)
+    meta: Dict[str, object] = field(default_factory=dict)
+
+    @property
+    def n_gates(self) -> int:
+        return len(self.schedule) * self.n_steps
+
+    @property
+    def words(self) -> int:
+        return (self.n + 63) // 64
+
+
+def tfim_observables(n: int, J: float, h: float, periodic: bool, zz_ranges: Sequence[int] = (1,)) -> Dict[str, Tuple[List[str], List[float]]]:
+    """<H>/n, <X_0>, <Z_0 Z_r> for the requested r, and M_x = sum X_i."""
+    strings, alphas, _ = tfim_terms(n, J, h, periodic)
+    obs: Dict[str, Tuple[List[str], List[float]]] = {}
+    obs["energy_per_site"] = (strings, [a / n for a in alphas])
+    obs["X0"] = ([single_site(n, 0, "X")], [1.0])
+    for r in zz_ranges:
+        if 0 < r < n:
+            obs[f"Z0Z{r}"] = ([two_site(n, 0, r, "Z", "Z")], [1.0])
+    obs["Mx"] = ([single_site(n, i, "X") for i in range(n)], [1.0] * n)
+    return obs
+
+
+def tfim_workload(name: str, n: int, J: float, h: float, periodic: bool, order: int,
+                  dtau: float, beta: float, delta: float, K: int, precision: str = "f64",
+                  zz_ranges: Sequence[int] = (1,)) -> Workload:
+    strings, alphas, n_zz = tfim_terms(n, J, h, periodic)
+    sched = tfim_schedule(n_zz, n, order)
+    return Workload(name=name, n=n, strings=strings, alphas=alphas, schedule=sched,
+                    dtau=dtau, n_steps=n_steps_for(beta, dtau), delta=delta, K=K,
+                    precision=precision,
+                    observables=tfim_observables(n, J, h, periodic, zz_ranges),
+                    meta=dict(model="tfim", J=J, h=h, periodic=periodic, order=order, beta=beta))
+
+
+# ---------------------------------------------------------------------------
+# The five benchmark workloads (synthetic TFIM instances; no dataset exists).
+# ---------------------------------------------------------------------------
+
+def config1() -> Workload:
+    """n=8 periodic TFIM, J=h=1, first order, dtau=0.05, beta 0->1 (20 steps),
+    threshold 1e-14, cap 2^20 (never reached)."""
+    return tfim_workload("tfim_n8_periodic_untruncated", 8, 1.0, 1.0, True, 1, 0.05, 1.0,
+                         1e-14, 1 << 20, zz_ranges=(1, 2, 3, 4))
+
+
+def config2_h(seed: int = 0) -> float:
+    return draw_uniform(seed, 0.5, 1.5)
+
+
+def config2(K: int = 1 << 24, beta: float = 2.0, seed: int = 0) -> Workload:
+    """n=64 open TFIM, J=1, h ~ U[0.5, 1.5] (seeded), Strang, dtau=0.02,
+    beta 0->2 (100 steps), threshold 1e-6, cap 2^24."""
+    h = config2_h(seed)
+    w = tfim_workload("tfim_n64_open_strang", 64, 1.0, h, False, 2, 0.02, beta, 1e-6, K,
+                      zz_ranges=tuple(range(1, 9)))
+    w.meta["seed"] = seed
+    return w
+
+
+def config3(K: int = 1 << 27, beta: float = 1.0, precision: str = "f32") -> Workload:
+    """n=128 periodic TFIM (two words), J=h=1, dtau=0.01, beta 0->1,
+    threshold 1e-7, cap 2^27."""
+    return tfim_workload("tfim_n128_periodic", 128, 1.0, 1.0, True, 1, 0.01, beta, 1e-7, K,
+                         precision=precision)
+
+
+def config4_instances(seed: int = 1, count: int = 64, K: int = 1 << 20) -> List[Workload]:
+    """64 periodic TFIM instances: n uniform in {16,24,...,128}, h ~ U[0.25,2],
+    beta ~ U[0.5,2], J=1, first order, dtau=0.02, threshold 1e-6, cap 2^20."""
+    rng = np.random.default_rng(seed)
+    sizes = np.arange(16, 129, 8)
+    ns = rng.choice(sizes, size=count)
+    hs = rng.uniform(0.25, 2.0, size=count)
+    betas = rng.uniform(0.5, 2.0, size=count)
+    out = []
+    for i in range(count):
+        w = tfim_workload(f"batch_{i}", int(ns[i]), 1.0, float(hs[i]), True, 1, 0.02,
+                          float(betas[i]), 1e-6, K)
+        out.append(w)
+    return out
+
+
+def config5(K: int = 1 << 24) -> Workload:
+    """n=64 periodic TFIM, J=h=1, first order, dtau=0.02, beta=1.5 (75 steps),
+    threshold 1e-6, cap 2^24."""
+    return tfim_workload("tfim_n64_periodic_adjoint", 64, 1.0, 1.0, True, 1, 0.02, 1.5, 1e-6, K)
+
+
+def paper_validation(n: int = 10, tau: float = 20.0) -> Workload:
+    """Sec. III validation run: open chain, J=1, h=0.5, dtau=0.04, no truncation."""
+    return tfim_workload(f"paper_validation_n{n}", n, 1.0, 0.5, False, 1, 0.04, tau, 0.0, 1 << 62)
+
+
+# ---------------------------------------------------------------------------
+# Random Hamiltonians with arbitrary Pauli letters (exercise Y phases).
+# ---------------------------------------------------------------------------
+
+def random_hamiltonian(n: int, n_terms: int, seed: int, max_weight: int = 3,
+                       local: bool = True) -> Tuple[List[str], List[float]]:
+    """Random real-weighted Pauli terms.  ``local`` draws supports from a window
+    of ``max_weight`` consecutive qubits (periodic), otherwise anywhere."""
+    rng = np.random.default_rng(seed)
+    strings: List[str] = []
+    alphas: List[float] = []
+    seen = set()
+    while len(strings) < n_terms:
+        w = int(rng.integers(1, max_weight + 1))
+        if local:
+            start = int(rng.integers(0, n))
+            window = [(start + k) % n for k in range(max_weight)]
+            sites = sorted(rng.choice(window, size=min(w, len(window)), replace=False).tolist())
+        else:
+            sites = sorted(rng.choice(n, size=w, replace=False).tolist())
+        s = ["I"] * n
+        for q in sites:
+            s[q] = "XYZ"[int(rng.integers(0, 3))]
+        key = "".join(s)
+        if key in seen or key == "I" * n:
+            continue
+        seen.add(key)
+        strings.append(key)
+        alphas.append(float(rng.uniform(-1.0, 1.0)))
+    return strings, alphas
+
+
+def random_workload(name: str, n: int, n_terms: int, seed: int, dtau: float, n_steps: int,
+                    delta: float, K: int, max_weight: int = 3, local: bool = True) -> Workload:
+    strings, alphas = random_hamiltonian(n, n_terms, seed, max_weight, local)
+    sched = [(k, 1.0) for k in range(n_terms)]
+    obs = {"energy": (list(strings), list(alphas))}
+    return Workload(name=name, n=n, strings=strings, alphas=alphas, schedule=sched, dtau=dtau,
+                    n_steps=n_steps, delta=delta, K=K, observables=obs,
+                    meta=dict(model="random", seed=seed))
+
+
+def random_pauli_strings(n: int, count: int, seed: int, density: float = 0.5) -> List[str]:
+    """Uniformly random strings (each site non-identity with probability ``density``)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        s = []
+        for _q in range(n):
+            if rng.random() < density:
+                s.append("XYZ"[int(rng.integers(0, 3))])
+            else:
+                s.append("I")
+        out.append("".join(s))
+    return out

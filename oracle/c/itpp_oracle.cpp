@@ -1,0 +1,225 @@
+// Plain C++ dictionary-of-strings ITPP oracle -- test infrastructure only.
+//
+// This is the C++ twin of oracle/itpp.py, written for speed on the host so
+// that larger parity cases and the CPU baseline run in seconds.  It follows
+// the same steps of Algorithm 1 of arXiv 2601.14400 in the same order and
+// shares no code with the GPU library:
+//   * strings are std::string over the letters I X Y Z (character j is
+//     qubit j) and products use the single-qubit table XY = iZ, YZ = iX,
+//     ZX = iY (Pauli algebra);
+//   * a gate exp(-(theta/2) Q) leaves an anticommuting P unchanged and maps
+//     a commuting P to cosh(theta) P - sinh(theta) Q P (Eq. ITPP_PropRules,
+//     Appendix A), theta = alpha_k * m * dtau;
+//   * contributions are accumulated in an std::unordered_map (the Pauli-basis
+//     re-expansion), truncated to |c| > delta (Sec. II.B) and, above K
+//     strings, to the identity plus the K-1 largest |c| with ties broken by
+//     the smaller (X, Z) bit integers (K-truncation, Sec. II.C);
+//   * every coefficient is then divided by the identity coefficient
+//     (normalisation after every elementary gate, Sec. II.C).
+// cosh/sinh come from the C library once per gate, so results agree bit for
+// bit with the Python oracle.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <utility>
+#include <vector>
+
+namespace {
+
+struct Prod {
+  int k;   // power of i
+  char r;  // resulting letter
+};
+
+Prod mul1(char a, char b) {
+  if (a == 'I') return {0, b};
+  if (b == 'I') return {0, a};
+  if (a == b) return {0, 'I'};
+  // cyclic X->Y->Z: a b = i c ; reversed: -i c
+  if ((a == 'X' && b == 'Y')) return {1, 'Z'};
+  if ((a == 'Y' && b == 'Z')) return {1, 'X'};
+  if ((a == 'Z' && b == 'X')) return {1, 'Y'};
+  if ((a == 'Y' && b == 'X')) return {3, 'Z'};
+  if ((a == 'Z' && b == 'Y')) return {3, 'X'};
+  return {3, 'Y'};  // X Z = -i Y
+}
+
+bool xbit(char a) { return a == 'X' || a == 'Y'; }
+bool zbit(char a) { return a == 'Z' || a == 'Y'; }
+
+// (X, Z) integer order, most significant qubit first.
+bool canonical_less(const std::string& p, const std::string& q) {
+  const int n = (int)p.size();
+  for (int j = n - 1; j >= 0; --j) {
+    bool a = xbit(p[j]), b = xbit(q[j]);
+    if (a != b) return b;
+  }
+  for (int j = n - 1; j >= 0; --j) {
+    bool a = zbit(p[j]), b = zbit(q[j]);
+    if (a != b) return b;
+  }
+  return false;
+}
+
+struct Oracle {
+  int n = 0;
+  std::unordered_map<std::string, double> S;
+  std::string err;
+  double term_updates = 0.0;
+  long long gates = 0;
+};
+
+}  // namespace
+
+extern "C" {
+
+void* itpp_oracle_new(int n) {
+  Oracle* o = new Oracle;
+  o->n = n;
+  o->S.emplace(std::string(n, 'I'), 1.0);
+  return o;
+}
+
+void itpp_oracle_free(void* h) { delete static_cast<Oracle*>(h); }
+
+const char* itpp_oracle_error(void* h) { return static_cast<Oracle*>(h)->err.c_str(); }
+
+// strings: n_terms * n characters, row-major.
+// Returns 0 on success, 1 if the identity coefficient is lost or not positive.
+int itpp_oracle_evolve(void* h, int n_terms, const char* strings, const double* alpha,
+                       int n_gates, const int* term_idx, const double* mult, double dtau,
+                       long long n_steps, double delta, long long K) {
+  Oracle* o = static_cast<Oracle*>(h);
+  const int n = o->n;
+  const std::string ident(n, 'I');
+  std::vector<std::string> terms(n_terms);
+  for (int k = 0; k < n_terms; ++k) terms[k] = std::string(strings + (size_t)k * n, n);
+  for (long long step = 0; step < n_steps; ++step) {
+    for (int g = 0; g < n_gates; ++g) {
+      const std::string& Q = terms[term_idx[g]];
+      if (Q == ident) continue;
+      const double theta = alpha[term_idx[g]] * mult[g] * dtau;
+      const double ch = std::cosh(theta);
+      const double sh = std::sinh(theta);
+      std::vector<int> sup;
+      for (int j = 0; j < n; ++j)
+        if (Q[j] != 'I') sup.push_back(j);
+      o->term_updates += (double)o->S.size();
+      // propagate and accumulate
+      std::unordered_map<std::string, double> out;
+      out.reserve(o->S.size() * 2 + 16);
+      for (const auto& kv : o->S) {
+        const std::string& P = kv.first;
+        const double c = kv.second;
+        int anti = 0;
+        for (int j : sup) {
+          char a = P[j], b = Q[j];
+          if (a != 'I' && a != b) ++anti;
+        }
+        if (anti % 2) {
+          out[P] += c;
+          continue;
+        }
+        std::string R = P;
+        int k = 0;
+        for (int j : sup) {
+          Prod pr = mul1(Q[j], P[j]);  // Q on the left
+          k += pr.k;
+          R[j] = pr.r;
+        }
+        k %= 4;
+        if (k % 2) {
+          o->err = "commuting strings gave an imaginary phase";
+          return 2;
+        }
+        const double sign = (k == 0) ? 1.0 : -1.0;
+        out[P] += ch * c;
+        out[R] += -sh * sign * c;
+      }
+      // truncate: threshold
+      std::vector<std::pair<std::string, double>> kept;
+      kept.reserve(out.size());
+      for (auto& kv : out)
+        if (std::fabs(kv.second) > delta) kept.emplace_back(kv.first, kv.second);
+      // truncate: cap
+      if ((long long)kept.size() > K) {
+        double cI = 0.0;
+        bool have = false;
+        std::vector<std::pair<std::string, double>> others;
+        others.reserve(kept.size());
+        for (auto& kv : kept) {
+          if (kv.first == ident) {
+            cI = kv.second;
+            have = true;
+          } else {
+            others.push_back(kv);
+          }
+        }
+        if (!have) {
+          o->err = "identity coefficient was truncated";
+          return 1;
+        }
+        auto better = [](const std::pair<std::string, double>& a,
+                         const std::pair<std::string, double>& b) {
+          double fa = std::fabs(a.second), fb = std::fabs(b.second);
+          if (fa != fb) return fa > fb;
+          return canonical_less(a.first, b.first);
+        };
+        const size_t keep = (size_t)(K - 1);
+        if (keep < others.size()) {
+          std::nth_element(others.begin(), others.begin() + keep, others.end(), better);
+          others.resize(keep);
+        }
+        kept.clear();
+        kept.emplace_back(ident, cI);
+        for (auto& kv : others) kept.push_back(kv);
+      }
+      // normalise
+      double cI = 0.0;
+      bool have = false;
+      for (auto& kv : kept)
+        if (kv.first == ident) {
+          cI = kv.second;
+          have = true;
+        }
+      if (!have || !(cI > 0.0) || !std::isfinite(cI)) {
+        o->err = "bad identity coefficient";
+        return 1;
+      }
+      o->S.clear();
+      o->S.reserve(kept.size() * 2);
+      for (auto& kv : kept) o->S.emplace(kv.first, kv.second / cI);
+      ++o->gates;
+    }
+  }
+  return 0;
+}
+
+long long itpp_oracle_size(void* h) { return (long long)static_cast<Oracle*>(h)->S.size(); }
+
+double itpp_oracle_term_updates(void* h) { return static_cast<Oracle*>(h)->term_updates; }
+
+// Writes the state in ascending (X, Z) order: strings (size*n chars) and coefs.
+void itpp_oracle_export(void* h, char* strings_out, double* coef_out) {
+  Oracle* o = static_cast<Oracle*>(h);
+  std::vector<const std::pair<const std::string, double>*> v;
+  v.reserve(o->S.size());
+  for (const auto& kv : o->S) v.push_back(&kv);
+  std::sort(v.begin(), v.end(), [](auto* a, auto* b) { return canonical_less(a->first, b->first); });
+  for (size_t i = 0; i < v.size(); ++i) {
+    std::memcpy(strings_out + i * o->n, v[i]->first.data(), o->n);
+    coef_out[i] = v[i]->second;
+  }
+}
+
+// Replaces the state (strings: count*n chars).
+void itpp_oracle_import(void* h, long long count, const char* strings, const double* coef) {
+  Oracle* o = static_cast<Oracle*>(h);
+  o->S.clear();
+  for (long long i = 0; i < count; ++i) o->S[std::string(strings + i * o->n, o->n)] = coef[i];
+}
+
+}  // extern "C"

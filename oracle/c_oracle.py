@@ -1,0 +1,110 @@
+"""ctypes wrapper of the plain C++ dictionary oracle in ``oracle/c``
+(test infrastructure only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Dict, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(_HERE, "c", "itpp_oracle.cpp")
+LIB = os.path.join(_HERE, "c", "libitpp_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(LIB):
+        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+               "-fno-fast-math", SRC, "-o", LIB + ".tmp"]
+        subprocess.check_call(cmd)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build(force=True)
+        lib = ctypes.CDLL(LIB)
+        lib.itpp_oracle_new.restype = ctypes.c_void_p
+        lib.itpp_oracle_new.argtypes = [ctypes.c_int]
+        lib.itpp_oracle_free.argtypes = [ctypes.c_void_p]
+        lib.itpp_oracle_error.restype = ctypes.c_char_p
+        lib.itpp_oracle_error.argtypes = [ctypes.c_void_p]
+        lib.itpp_oracle_evolve.restype = ctypes.c_int
+        lib.itpp_oracle_evolve.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_char_p,
+                                           ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_double, ctypes.c_longlong,
+                                           ctypes.c_double, ctypes.c_longlong]
+        lib.itpp_oracle_size.restype = ctypes.c_longlong
+        lib.itpp_oracle_size.argtypes = [ctypes.c_void_p]
+        lib.itpp_oracle_term_updates.restype = ctypes.c_double
+        lib.itpp_oracle_term_updates.argtypes = [ctypes.c_void_p]
+        lib.itpp_oracle_export.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        lib.itpp_oracle_import.argtypes = [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_char_p,
+                                           ctypes.c_void_p]
+        _lib = lib
+    return _lib
+
+
+class COracle:
+    def __init__(self, n: int):
+        self.n = n
+        self._lib = _load()
+        self._h = self._lib.itpp_oracle_new(n)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.itpp_oracle_free(h)
+            self._h = None
+
+    def evolve(self, strings: Sequence[str], alphas: Sequence[float],
+               schedule: Sequence[Tuple[int, float]], dtau: float, n_steps: int,
+               delta: float, K: int) -> None:
+        buf = "".join(strings).encode("ascii")
+        a = np.ascontiguousarray(alphas, dtype=np.float64)
+        ti = np.ascontiguousarray([k for k, _ in schedule], dtype=np.int32)
+        mu = np.ascontiguousarray([m for _, m in schedule], dtype=np.float64)
+        rc = self._lib.itpp_oracle_evolve(self._h, len(strings), buf, a.ctypes.data, len(schedule),
+                                          ti.ctypes.data, mu.ctypes.data, float(dtau),
+                                          int(n_steps), float(delta), int(K))
+        if rc != 0:
+            raise RuntimeError(self._lib.itpp_oracle_error(self._h).decode())
+
+    def size(self) -> int:
+        return int(self._lib.itpp_oracle_size(self._h))
+
+    def term_updates(self) -> float:
+        return float(self._lib.itpp_oracle_term_updates(self._h))
+
+    def export(self) -> Tuple[list, np.ndarray]:
+        m = self.size()
+        sbuf = ctypes.create_string_buffer(m * self.n + 1)
+        coef = np.empty(m, dtype=np.float64)
+        self._lib.itpp_oracle_export(self._h, sbuf, coef.ctypes.data)
+        raw = sbuf.raw[: m * self.n].decode("ascii")
+        strings = [raw[i * self.n:(i + 1) * self.n] for i in range(m)]
+        return strings, coef
+
+    def state(self) -> Dict[str, float]:
+        s, c = self.export()
+        return dict(zip(s, c.tolist()))
+
+    def load(self, S: Dict[str, float]) -> None:
+        keys = list(S)
+        buf = "".join(keys).encode("ascii")
+        coef = np.ascontiguousarray([S[k] for k in keys], dtype=np.float64)
+        self._lib.itpp_oracle_import(self._h, len(keys), buf, coef.ctypes.data)
+
+
+def run_workload(w, n_steps=None, K=None) -> COracle:
+    o = COracle(w.n)
+    o.evolve(w.strings, w.alphas, w.schedule, w.dtau, w.n_steps if n_steps is None else n_steps,
+             w.delta, w.K if K is None else K)
+    return o
