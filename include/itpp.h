@@ -1,0 +1,145 @@
+/*
+ * itpp.h -- C ABI of the MI355X (gfx950) imaginary-time Pauli propagation
+ * engine (arXiv 2601.14400, "Pauli Propagation for Imaginary-Time Evolution").
+ *
+ * The engine keeps a density matrix rho = 2^-n sum_P a_P P as a sparse set of
+ * Pauli strings with real coefficients, starting from rho = I (the identity is
+ * propagated instead of I/2^n, Sec. II.C), and applies one elementary gate
+ * V_Q = exp(-(theta/2) Q) at a time with the imaginary-time rule of
+ * Eq. (ITPP_PropRules): a string anticommuting with Q is unchanged, a
+ * commuting string P becomes cosh(theta) P - sinh(theta) Q P.  After every
+ * gate the strings are merged, truncated (keep |c| > threshold; above
+ * max_terms strings keep the identity and the max_terms-1 largest |c|, ties
+ * broken by the smaller canonical key) and divided by the identity
+ * coefficient (Algorithm 1; per-gate normalisation as Sec. II.C requires).
+ *
+ * Conventions shared by every entry point
+ * --------------------------------------
+ *  - Pauli strings are packed as W = ceil(n/64) little-endian uint64 words of
+ *    x bits followed (in a separate array) by W words of z bits; qubit j is
+ *    bit (j % 64) of word (j / 64).  (x,z) = (0,0) I, (1,0) X, (0,1) Z,
+ *    (1,1) Y, and P(x,z) = i^{|x & z|} X^x Z^z, so every string is Hermitian.
+ *    Arrays of strings are string-major: string s occupies words
+ *    [s*W, s*W + W).  Bits at or above n must be zero.
+ *  - The canonical key order (used for cap ties and for itpp_export) compares
+ *    the x bits as one n-bit integer, then the z bits as one n-bit integer.
+ *  - Gate angle: theta = alpha[term] * mult[gate] * dtau, evaluated left to
+ *    right in IEEE double; cosh and sinh are taken once per gate on the host.
+ *  - All pointers are host pointers; the caller owns them, the library copies
+ *    what it needs during the call and keeps no reference.  Device state is
+ *    owned by the context.
+ *  - Every call returns an itpp_status; ITPP_OK is 0.  On error nothing is
+ *    written to output arguments and itpp_last_error() describes the cause.
+ *  - A context is used from one host thread at a time.
+ */
+#ifndef ITPP_H_
+#define ITPP_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct itpp_ctx_s* itpp_ctx;
+
+typedef enum {
+  ITPP_OK = 0,
+  ITPP_ERR_ARG = 1,      /* invalid argument (message says which) */
+  ITPP_ERR_OOM = 2,      /* device memory for the requested cap is not available */
+  ITPP_ERR_CAP = 3,      /* cap reached under ITPP_CAP_FAIL */
+  ITPP_ERR_NUMERIC = 4,  /* identity coefficient not finite or not positive */
+  ITPP_ERR_DEVICE = 5,   /* HIP runtime error or missing gfx950 device */
+  ITPP_ERR_STATE = 6     /* call out of order (e.g. evolve before set_schedule) */
+} itpp_status;
+
+typedef enum { ITPP_F64 = 0, ITPP_F32 = 1 } itpp_precision;
+
+/* What to do when more than max_terms strings survive the threshold
+ * (Sec. II.C, practical considerations): keep the largest (K-truncation) or
+ * stop with ITPP_ERR_CAP. */
+typedef enum { ITPP_CAP_TOPK = 0, ITPP_CAP_FAIL = 1 } itpp_cap_policy;
+
+typedef struct {
+  int32_t n_qubits;           /* 1..128 */
+  int32_t precision;          /* itpp_precision; ITPP_F64 only in this version */
+  double threshold;           /* delta >= 0, keep |c| > delta (Sec. II.B); delta < 1 */
+  int64_t max_terms;          /* K >= 1: the identity plus at most K-1 others */
+  int32_t cap_policy;         /* itpp_cap_policy */
+  int32_t reserved0;
+  void* stream;               /* hipStream_t to run on, or NULL for the null stream */
+  int64_t device_bytes_limit; /* 0: no limit; else fail create with ITPP_ERR_OOM above it */
+} itpp_config;
+
+typedef struct {
+  int64_t n_terms;       /* strings in the current state (after truncation) */
+  int64_t n_gates;       /* elementary gates applied by the last evolve */
+  double term_updates;   /* sum over those gates of the strings entering the gate */
+  double c_identity;     /* identity coefficient before the last normalisation */
+  int32_t cap_hit;       /* 1 if the cap truncated at least one gate */
+  int32_t reserved0;
+} itpp_stats;
+
+/* Create a context on the current HIP device.  Validation (ITPP_ERR_ARG):
+ * n_qubits outside 1..128, threshold negative, not finite or >= 1,
+ * max_terms < 1, unknown precision or cap policy.  ITPP_ERR_DEVICE if no
+ * gfx950 device is current.  Allocates the state buffers (about
+ * 8 * max_terms * (16W + 8) bytes); ITPP_ERR_OOM if that fails or exceeds
+ * device_bytes_limit.  The state starts as rho = I. */
+itpp_status itpp_create(const itpp_config* cfg, itpp_ctx* out);
+
+/* Free the context and its device memory.  NULL is accepted. */
+itpp_status itpp_destroy(itpp_ctx ctx);
+
+/* Hamiltonian H = sum_k alpha_k Q_k (Algorithm 1 input).  x, z: n_terms*W
+ * words each; alpha: n_terms finite doubles.  A term may flip at most two
+ * bits (|x| + |z| <= 2 over its words: one- and two-letter X/Z terms and
+ * single-site Y); others give ITPP_ERR_ARG.  Identity terms are accepted and
+ * skipped as gates.  Replaces any previous Hamiltonian and schedule. */
+itpp_status itpp_set_hamiltonian(itpp_ctx ctx, int32_t n_terms, const uint64_t* x,
+                                 const uint64_t* z, const double* alpha);
+
+/* One Trotter step as a gate list: gate g applies term term_idx[g] with
+ * multiplier mult[g] (first order: every term once with 1; Strang: A at 1/2,
+ * B at 1, A at 1/2; Sec. II.C).  Indices must be in range, mult finite. */
+itpp_status itpp_set_schedule(itpp_ctx ctx, int32_t n_gates, const int32_t* term_idx,
+                              const double* mult);
+
+/* Reset the state to rho = I (a single identity string with coefficient 1). */
+itpp_status itpp_reset(itpp_ctx ctx);
+
+/* Apply n_steps Trotter steps of the schedule with step dtau > 0 (finite).
+ * Runs asynchronously on cfg.stream except for the final status check; st
+ * (nullable) receives the statistics of this call.  ITPP_ERR_CAP under
+ * ITPP_CAP_FAIL when a gate leaves more than max_terms strings (the state is
+ * then that of the last completed gate); ITPP_ERR_NUMERIC if the identity
+ * coefficient is not finite and positive. */
+itpp_status itpp_evolve(itpp_ctx ctx, double dtau, int64_t n_steps, itpp_stats* st);
+
+/* <O> = sum_j coef[j] * a_{P_j} for O = sum_j coef[j] P_j (Eq.
+ * Expectation_Value in the Pauli basis; absent strings count 0), summed in
+ * FP64 with compensation on the device.  out receives one double. */
+itpp_status itpp_expect(itpp_ctx ctx, int32_t n_strings, const uint64_t* x, const uint64_t* z,
+                        const double* coef, double* out);
+
+/* Number of strings in the current (truncated) state, identity included. */
+itpp_status itpp_num_terms(itpp_ctx ctx, int64_t* out);
+
+/* Copy the current state in ascending canonical key order: x, z receive
+ * n*W words each, coef n normalised coefficients (identity = 1).  If
+ * capacity is smaller than the number of strings, nothing is copied and
+ * *n_out receives the required capacity with ITPP_ERR_ARG. */
+itpp_status itpp_export(itpp_ctx ctx, int64_t capacity, uint64_t* x, uint64_t* z, double* coef,
+                        int64_t* n_out);
+
+/* Message for the last error on ctx (static string for ctx == NULL). */
+const char* itpp_last_error(itpp_ctx ctx);
+
+/* Library build information ("gfx950 ..."). */
+const char* itpp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ITPP_H_ */

@@ -1,0 +1,220 @@
+"""ctypes binding of ``libitpp.so`` (argument marshalling only).
+
+Every step of the propagation runs in the library's HIP kernels; this module
+converts Python strings and lists to the packed words and arrays the C ABI
+takes and turns status codes into exceptions.  There is no fallback: if the
+library is missing, importing the engine fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libitpp.so")
+
+STATUS = {0: "ITPP_OK", 1: "ITPP_ERR_ARG", 2: "ITPP_ERR_OOM", 3: "ITPP_ERR_CAP",
+          4: "ITPP_ERR_NUMERIC", 5: "ITPP_ERR_DEVICE", 6: "ITPP_ERR_STATE"}
+
+# Every entry point declared in include/itpp.h.
+EXPORTED = ["itpp_create", "itpp_destroy", "itpp_set_hamiltonian", "itpp_set_schedule",
+            "itpp_reset", "itpp_evolve", "itpp_expect", "itpp_num_terms", "itpp_export",
+            "itpp_last_error", "itpp_version"]
+
+
+class ItppConfig(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("threshold", ctypes.c_double), ("max_terms", ctypes.c_int64),
+                ("cap_policy", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("stream", ctypes.c_void_p), ("device_bytes_limit", ctypes.c_int64)]
+
+
+class ItppStats(ctypes.Structure):
+    _fields_ = [("n_terms", ctypes.c_int64), ("n_gates", ctypes.c_int64),
+                ("term_updates", ctypes.c_double), ("c_identity", ctypes.c_double),
+                ("cap_hit", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+
+
+class ItppError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: Optional[str] = None):
+    """Load libitpp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"{p} is missing: build it with paper_2601_14400_amd.build.build()")
+    # One HIP runtime per process: load PyTorch's first so that the library's
+    # libamdhip64.so.7 dependency binds to the runtime torch already uses (a
+    # stream or device pointer from torch is then valid in the library).
+    try:
+        import torch  # noqa: F401
+    except Exception:
+        pass
+    lib = ctypes.CDLL(p)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.itpp_create.argtypes = [ctypes.POINTER(ItppConfig), ctypes.POINTER(vp)]
+    lib.itpp_destroy.argtypes = [vp]
+    lib.itpp_set_hamiltonian.argtypes = [vp, i32, vp, vp, vp]
+    lib.itpp_set_schedule.argtypes = [vp, i32, vp, vp]
+    lib.itpp_reset.argtypes = [vp]
+    lib.itpp_evolve.argtypes = [vp, dbl, i64, ctypes.POINTER(ItppStats)]
+    lib.itpp_expect.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(dbl)]
+    lib.itpp_num_terms.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.itpp_export.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(i64)]
+    lib.itpp_last_error.argtypes = [vp]
+    lib.itpp_last_error.restype = ctypes.c_char_p
+    lib.itpp_version.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name not in ("itpp_last_error", "itpp_version"):
+            getattr(lib, name).restype = ctypes.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def strings_to_words(strings: Sequence[str], n: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Pack 'IXYZ' strings (character j = qubit j) into x/z words."""
+    W = (n + 63) // 64
+    x = np.zeros((len(strings), W), dtype=np.uint64)
+    z = np.zeros((len(strings), W), dtype=np.uint64)
+    for s, P in enumerate(strings):
+        if len(P) != n:
+            raise ValueError(f"string length {len(P)} != n_qubits {n}")
+        for j, a in enumerate(P):
+            if a == "I":
+                continue
+            bit = np.uint64(1) << np.uint64(j & 63)
+            if a in "XY":
+                x[s, j >> 6] |= bit
+            if a in "ZY":
+                z[s, j >> 6] |= bit
+            if a not in "XYZ":
+                raise ValueError(f"bad Pauli letter {a!r}")
+    return x, z
+
+
+def words_to_strings(x: np.ndarray, z: np.ndarray, n: int) -> List[str]:
+    out = []
+    for s in range(x.shape[0]):
+        letters = []
+        for j in range(n):
+            xb = (int(x[s, j >> 6]) >> (j & 63)) & 1
+            zb = (int(z[s, j >> 6]) >> (j & 63)) & 1
+            letters.append("IXZY"[xb | (zb << 1)])
+        out.append("".join(letters))
+    return out
+
+
+def _current_stream():
+    try:
+        import torch
+
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return ctypes.c_void_p(None)
+
+
+class Engine:
+    """One ITPP state on the current HIP device (see include/itpp.h)."""
+
+    def __init__(self, n_qubits: int, threshold: float, max_terms: int, precision: str = "f64",
+                 cap_policy: str = "topk", stream=None, device_bytes_limit: int = 0):
+        self._lib = load_library()
+        self.n = int(n_qubits)
+        self.W = (self.n + 63) // 64
+        cfg = ItppConfig()
+        cfg.n_qubits = self.n
+        cfg.precision = {"f64": 0, "f32": 1}[precision]
+        cfg.threshold = float(threshold)
+        cfg.max_terms = int(max_terms)
+        cfg.cap_policy = {"topk": 0, "fail": 1}[cap_policy]
+        cfg.stream = stream if stream is not None else _current_stream()
+        cfg.device_bytes_limit = int(device_bytes_limit)
+        h = ctypes.c_void_p()
+        rc = self._lib.itpp_create(ctypes.byref(cfg), ctypes.byref(h))
+        if rc != 0:
+            msg = self._lib.itpp_last_error(None)
+            raise ItppError(rc, "itpp_create: " + (msg.decode() if msg else ""))
+        self._h = h
+
+    def _check(self, rc: int):
+        if rc != 0:
+            msg = self._lib.itpp_last_error(self._h)
+            raise ItppError(rc, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.itpp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_hamiltonian(self, strings: Sequence[str], alphas: Sequence[float]):
+        x, z = strings_to_words(strings, self.n)
+        a = np.ascontiguousarray(alphas, dtype=np.float64)
+        self._check(self._lib.itpp_set_hamiltonian(self._h, len(strings), x.ctypes.data,
+                                                   z.ctypes.data, a.ctypes.data))
+
+    def set_schedule(self, schedule: Sequence[Tuple[int, float]]):
+        ti = np.ascontiguousarray([k for k, _ in schedule], dtype=np.int32)
+        mu = np.ascontiguousarray([m for _, m in schedule], dtype=np.float64)
+        self._check(self._lib.itpp_set_schedule(self._h, len(schedule), ti.ctypes.data, mu.ctypes.data))
+
+    def reset(self):
+        self._check(self._lib.itpp_reset(self._h))
+
+    def evolve(self, dtau: float, n_steps: int) -> Dict[str, float]:
+        st = ItppStats()
+        self._check(self._lib.itpp_evolve(self._h, float(dtau), int(n_steps), ctypes.byref(st)))
+        return {"n_terms": st.n_terms, "n_gates": st.n_gates, "term_updates": st.term_updates,
+                "c_identity": st.c_identity, "cap_hit": st.cap_hit}
+
+    def expect(self, strings: Sequence[str], coefs: Sequence[float]) -> float:
+        x, z = strings_to_words(strings, self.n)
+        c = np.ascontiguousarray(coefs, dtype=np.float64)
+        out = ctypes.c_double()
+        self._check(self._lib.itpp_expect(self._h, len(strings), x.ctypes.data, z.ctypes.data,
+                                          c.ctypes.data, ctypes.byref(out)))
+        return float(out.value)
+
+    def num_terms(self) -> int:
+        v = ctypes.c_int64()
+        self._check(self._lib.itpp_num_terms(self._h, ctypes.byref(v)))
+        return int(v.value)
+
+    def export(self) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+        m = self.num_terms()
+        x = np.zeros((max(m, 1), self.W), dtype=np.uint64)
+        z = np.zeros((max(m, 1), self.W), dtype=np.uint64)
+        c = np.zeros(max(m, 1), dtype=np.float64)
+        n_out = ctypes.c_int64()
+        self._check(self._lib.itpp_export(self._h, m, x.ctypes.data, z.ctypes.data, c.ctypes.data,
+                                          ctypes.byref(n_out)))
+        k = int(n_out.value)
+        return x[:k], z[:k], c[:k]
+
+    def state(self) -> Dict[str, float]:
+        x, z, c = self.export()
+        return dict(zip(words_to_strings(x, z, self.n), c.tolist()))
+
+
+def version() -> str:
+    return load_library().itpp_version().decode()

@@ -1,0 +1,551 @@
+// Host runtime and C ABI of the ITPP engine (see include/itpp.h).
+//
+// The host owns the schedule and the bit permutation ("rep") of the stored
+// keys.  For every elementary gate it computes cosh/sinh of the angle
+// theta = alpha_k * m * dtau (Algorithm 1, Eq. ITPP_PropRules), the rep
+// positions of the bits the gate tests and flips, and the move of the next
+// gate's flip bits to the top of the rep; it then enqueues the gate kernel
+// and the selection kernels on the context's stream without waiting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/itpp.h"
+#include "itpp_internal.h"
+
+using namespace itpp;
+
+namespace {
+
+struct TermInfo {
+  std::vector<uint64_t> x, z;  // canonical words
+  double alpha = 0.0;
+  bool identity = true;
+  std::vector<int> F;      // canonical bits flipped (x_j -> j, z_j -> n + j), ascending
+  std::vector<int> cbits;  // canonical bits whose parity marks anticommutation
+  int nsup = 0;
+  int sup[2] = {0, 0};
+  int qx[2] = {0, 0}, qz[2] = {0, 0};
+  int aQ = 0;
+};
+
+}  // namespace
+
+struct itpp_ctx_s {
+  itpp_config cfg{};
+  int n = 0, W = 1, NW = 2, nbits = 2;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int cus = 256;
+  uint64_t cap = 0;  // elements per side
+  Side side[2]{};
+  Plan* plan = nullptr;    // [2]
+  Filter* filt = nullptr;  // [2]
+  Ctl* ctl = nullptr;
+  TileStatus* status = nullptr;
+  uint64_t status_cap = 0;
+  SelBuf sel{};
+  double* d_result = nullptr;
+  std::vector<void*> allocs;
+  // model
+  std::vector<TermInfo> terms;
+  std::vector<int> sched_term;
+  std::vector<double> sched_mult;
+  std::vector<int> glist;  // schedule positions of non-identity gates
+  // state
+  std::vector<int> pos;  // canonical bit -> rep position of the stored state
+  int cur = 0;           // side holding the stored state
+  int par = 0;           // plan/filter slot describing the stored state
+  bool ready = false;
+  uint32_t epoch = 1;
+  std::string err;
+};
+
+namespace {
+
+const char* kVersion = "itpp gfx950 merge-join engine 0.1";
+thread_local std::string g_create_error = "no error";
+
+itpp_status create_fail(itpp_status s, const std::string& m) {
+  g_create_error = m;
+  return s;
+}
+
+itpp_status fail(itpp_ctx c, itpp_status s, const std::string& m) {
+  if (c) c->err = m;
+  return s;
+}
+
+itpp_status hip_fail(itpp_ctx c, hipError_t e, const char* where) {
+  return fail(c, ITPP_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr)                              \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+  } while (0)
+
+void move_top(std::vector<int>& pos, int cb, int nbits, int* old_pos) {
+  const int p = pos[cb];
+  if (old_pos) *old_pos = p;
+  for (auto& q : pos)
+    if (q > p) --q;
+  pos[cb] = nbits - 1;
+}
+
+int popcount_words(const std::vector<uint64_t>& v) {
+  int s = 0;
+  for (auto w : v) s += __builtin_popcountll(w);
+  return s;
+}
+
+void free_all(itpp_ctx c) {
+  for (void* p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+}
+
+template <typename T>
+hipError_t dalloc(itpp_ctx c, T** p, size_t count) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+  if (e == hipSuccess) {
+    c->allocs.push_back(q);
+    *p = static_cast<T*>(q);
+  }
+  return e;
+}
+
+// Initial rep: identity permutation with the first gate's flip bits on top.
+void reset_rep(itpp_ctx c) {
+  c->pos.resize(c->nbits);
+  for (int i = 0; i < c->nbits; ++i) c->pos[i] = i;
+  if (!c->glist.empty()) {
+    const TermInfo& t = c->terms[c->sched_term[c->glist[0]]];
+    for (int b : t.F) move_top(c->pos, b, c->nbits, nullptr);
+  }
+}
+
+itpp_status do_reset(itpp_ctx c) {
+  reset_rep(c);
+  int w0 = 0;
+  if (!c->glist.empty()) w0 = (int)c->terms[c->sched_term[c->glist[0]]].F.size();
+  c->cur = 0;
+  c->par = 0;
+  HIP_TRY(c, launch_init(c->NW, c->side[0], c->plan + 0, c->filt + 0, c->ctl, w0, c->stream));
+  c->ready = true;
+  return ITPP_OK;
+}
+
+itpp_status check_error(itpp_ctx c) {
+  Ctl h{};
+  HIP_TRY(c, hipMemcpyAsync(&h, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  switch (h.error) {
+    case kErrNone:
+      return ITPP_OK;
+    case kErrNumeric:
+      c->ready = false;
+      return fail(c, ITPP_ERR_NUMERIC, "identity coefficient not finite or not positive; reset required");
+    case kErrCap:
+      c->ready = false;
+      return fail(c, ITPP_ERR_CAP, "more than max_terms strings survived the threshold (ITPP_CAP_FAIL); reset required");
+    case kErrPhase:
+      c->ready = false;
+      return fail(c, ITPP_ERR_DEVICE, "internal error: imaginary phase for commuting strings");
+    case kErrSpin:
+      c->ready = false;
+      return fail(c, ITPP_ERR_DEVICE, "internal error: look-back wait exceeded its bound");
+    default:
+      c->ready = false;
+      return fail(c, ITPP_ERR_DEVICE, "internal error: device buffer bound exceeded");
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* itpp_version(void) { return kVersion; }
+
+const char* itpp_last_error(itpp_ctx ctx) {
+  if (!ctx) return g_create_error.c_str();
+  return ctx->err.c_str();
+}
+
+itpp_status itpp_create(const itpp_config* cfg, itpp_ctx* out) {
+  if (!cfg || !out) return create_fail(ITPP_ERR_ARG, "null argument");
+  if (cfg->n_qubits < 1 || cfg->n_qubits > 64 * kMaxWords)
+    return create_fail(ITPP_ERR_ARG, "n_qubits must be in 1..128");
+  if (!(cfg->threshold >= 0.0) || !std::isfinite(cfg->threshold) || cfg->threshold >= 1.0)
+    return create_fail(ITPP_ERR_ARG, "threshold must be finite, >= 0 and < 1");
+  if (cfg->max_terms < 1) return create_fail(ITPP_ERR_ARG, "max_terms must be >= 1");
+  if (cfg->precision != ITPP_F64) return create_fail(ITPP_ERR_ARG, "only ITPP_F64 is supported");
+  if (cfg->cap_policy != ITPP_CAP_TOPK && cfg->cap_policy != ITPP_CAP_FAIL)
+    return create_fail(ITPP_ERR_ARG, "unknown cap policy");
+  int dev = 0;
+  hipError_t he = hipGetDevice(&dev);
+  if (he != hipSuccess) return create_fail(ITPP_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(he));
+  hipDeviceProp_t prop;
+  he = hipGetDeviceProperties(&prop, dev);
+  if (he != hipSuccess)
+    return create_fail(ITPP_ERR_DEVICE, std::string("hipGetDeviceProperties: ") + hipGetErrorString(he));
+  if (std::string(prop.gcnArchName).rfind("gfx950", 0) != 0)
+    return create_fail(ITPP_ERR_DEVICE, std::string("device is ") + prop.gcnArchName + ", not gfx950");
+
+  itpp_ctx c = new (std::nothrow) itpp_ctx_s;
+  if (!c) return ITPP_ERR_OOM;
+  c->cfg = *cfg;
+  c->n = cfg->n_qubits;
+  c->W = (c->n + 63) / 64;
+  c->NW = 2 * c->W;
+  c->nbits = 2 * c->n;
+  c->stream = static_cast<hipStream_t>(cfg->stream);
+  c->device = dev;
+  c->cus = prop.multiProcessorCount;
+  // every stored string comes from at most two outputs of a survivor and the
+  // next gate's regions reserve twice the stored count: 4 K elements per side
+  uint64_t kmax = (uint64_t)cfg->max_terms;
+  if (c->n <= 30) kmax = std::min<uint64_t>(kmax, 1ull << (2 * c->n));
+  c->cap = 4 * kmax + 64;
+  const uint64_t elem_bytes = (uint64_t)c->NW * 8 + 8;
+  const int tile = gate_tile(c->NW);
+  c->status_cap = c->cap / (uint64_t)tile + 16;
+  const uint64_t sel_cap = 2 * kmax + 64;
+  const uint64_t bytes = 2 * c->cap * elem_bytes + c->status_cap * sizeof(TileStatus) +
+                         sel_cap * (16 + 8 * (uint64_t)c->NW) + 4096;
+  if (cfg->device_bytes_limit > 0 && bytes > (uint64_t)cfg->device_bytes_limit) {
+    delete c;
+    return create_fail(ITPP_ERR_OOM, "state buffers exceed device_bytes_limit");
+  }
+  bool ok = true;
+  for (int s = 0; s < 2 && ok; ++s) {
+    for (int q = 0; q < c->NW && ok; ++q) ok = dalloc(c, &c->side[s].kw[q], c->cap) == hipSuccess;
+    if (ok) ok = dalloc(c, &c->side[s].coef, c->cap) == hipSuccess;
+  }
+  if (ok) ok = dalloc(c, &c->plan, 2) == hipSuccess;
+  if (ok) ok = dalloc(c, &c->filt, 2) == hipSuccess;
+  if (ok) ok = dalloc(c, &c->ctl, 1) == hipSuccess;
+  if (ok) ok = dalloc(c, &c->status, c->status_cap) == hipSuccess;
+  if (ok) ok = dalloc(c, &c->sel.cand_bits, sel_cap) == hipSuccess;
+  if (ok) ok = dalloc(c, &c->sel.cand_idx, sel_cap) == hipSuccess;
+  if (ok) ok = dalloc(c, &c->sel.tie_keys, sel_cap * c->NW) == hipSuccess;
+  if (ok) ok = dalloc(c, &c->d_result, 4) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    free_all(c);
+    delete c;
+    return create_fail(ITPP_ERR_OOM, "hipMalloc of the state buffers failed");
+  }
+  c->sel.cap = sel_cap;
+  he = hipMemsetAsync(c->status, 0, c->status_cap * sizeof(TileStatus), c->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(c->plan, 0, 2 * sizeof(Plan), c->stream);
+  if (he != hipSuccess) {
+    free_all(c);
+    delete c;
+    return create_fail(ITPP_ERR_DEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(he));
+  }
+  if (do_reset(c) != ITPP_OK) {
+    std::string m = c->err;
+    free_all(c);
+    delete c;
+    return create_fail(ITPP_ERR_DEVICE, "initial state: " + m);
+  }
+  *out = c;
+  return ITPP_OK;
+}
+
+itpp_status itpp_destroy(itpp_ctx ctx) {
+  if (!ctx) return ITPP_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  free_all(ctx);
+  delete ctx;
+  return ITPP_OK;
+}
+
+itpp_status itpp_set_hamiltonian(itpp_ctx c, int32_t n_terms, const uint64_t* x, const uint64_t* z,
+                                 const double* alpha) {
+  if (!c) return ITPP_ERR_ARG;
+  if (n_terms < 1 || !x || !z || !alpha) return fail(c, ITPP_ERR_ARG, "empty Hamiltonian");
+  const int W = c->W, n = c->n;
+  std::vector<TermInfo> terms(n_terms);
+  for (int k = 0; k < n_terms; ++k) {
+    TermInfo& t = terms[k];
+    t.x.assign(x + (size_t)k * W, x + (size_t)k * W + W);
+    t.z.assign(z + (size_t)k * W, z + (size_t)k * W + W);
+    for (int q = 0; q < W; ++q) {
+      const int hi = n - 64 * q;
+      if (hi < 64) {
+        const uint64_t bad = hi <= 0 ? ~0ull : ~((1ull << hi) - 1ull);
+        if ((t.x[q] | t.z[q]) & bad) return fail(c, ITPP_ERR_ARG, "term has bits at or above n_qubits");
+      }
+    }
+    if (!std::isfinite(alpha[k])) return fail(c, ITPP_ERR_ARG, "non-finite term weight");
+    t.alpha = alpha[k];
+    const int flips = popcount_words(t.x) + popcount_words(t.z);
+    if (flips > kMaxClassBits)
+      return fail(c, ITPP_ERR_ARG, "term flips more than two bits (|x| + |z| > 2): not supported");
+    t.identity = flips == 0;
+    for (int j = 0; j < n; ++j) {
+      const int xj = (t.x[j >> 6] >> (j & 63)) & 1, zj = (t.z[j >> 6] >> (j & 63)) & 1;
+      if (xj) t.F.push_back(j);
+      if (zj) t.F.push_back(n + j);
+      if (zj) t.cbits.push_back(j);      // x_P z_Q
+      if (xj) t.cbits.push_back(n + j);  // z_P x_Q
+      if (xj || zj) {
+        t.sup[t.nsup] = j;
+        t.qx[t.nsup] = xj;
+        t.qz[t.nsup] = zj;
+        ++t.nsup;
+        if (xj && zj) ++t.aQ;
+      }
+    }
+    std::sort(t.F.begin(), t.F.end());
+  }
+  c->terms.swap(terms);
+  c->sched_term.clear();
+  c->sched_mult.clear();
+  c->glist.clear();
+  c->ready = false;
+  return ITPP_OK;
+}
+
+itpp_status itpp_set_schedule(itpp_ctx c, int32_t n_gates, const int32_t* term_idx, const double* mult) {
+  if (!c) return ITPP_ERR_ARG;
+  if (c->terms.empty()) return fail(c, ITPP_ERR_STATE, "set_hamiltonian first");
+  if (n_gates < 1 || !term_idx || !mult) return fail(c, ITPP_ERR_ARG, "empty schedule");
+  std::vector<int> st(n_gates), gl;
+  std::vector<double> sm(n_gates);
+  for (int g = 0; g < n_gates; ++g) {
+    if (term_idx[g] < 0 || term_idx[g] >= (int)c->terms.size())
+      return fail(c, ITPP_ERR_ARG, "schedule term index out of range");
+    if (!std::isfinite(mult[g])) return fail(c, ITPP_ERR_ARG, "non-finite schedule multiplier");
+    st[g] = term_idx[g];
+    sm[g] = mult[g];
+    if (!c->terms[st[g]].identity) gl.push_back(g);
+  }
+  c->sched_term.swap(st);
+  c->sched_mult.swap(sm);
+  c->glist.swap(gl);
+  return do_reset(c);
+}
+
+itpp_status itpp_reset(itpp_ctx c) {
+  if (!c) return ITPP_ERR_ARG;
+  return do_reset(c);
+}
+
+itpp_status itpp_evolve(itpp_ctx c, double dtau, int64_t n_steps, itpp_stats* st) {
+  if (!c) return ITPP_ERR_ARG;
+  if (c->sched_term.empty()) return fail(c, ITPP_ERR_STATE, "set_schedule first");
+  if (!(dtau > 0.0) || !std::isfinite(dtau)) return fail(c, ITPP_ERR_ARG, "dtau must be finite and > 0");
+  if (n_steps < 0) return fail(c, ITPP_ERR_ARG, "n_steps must be >= 0");
+  if (!c->ready) {
+    itpp_status s = do_reset(c);
+    if (s != ITPP_OK) return s;
+  }
+  // zero the run statistics
+  Ctl h0{};
+  HIP_TRY(c, hipMemcpyAsync(&h0, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (h0.error) return check_error(c);
+  const double tu0 = h0.term_updates;
+  const uint64_t g0 = h0.gates;
+  const int G = (int)c->glist.size();
+  const int grid = c->cus * 3;
+  const int sel_grid = c->cus * 4;
+  const int tile = gate_tile(c->NW);
+  const int nbits = c->nbits;
+  GateParams gp{};
+  RepPos rp{};
+  rp.nbits = nbits;
+  for (int64_t s = 0; s < n_steps && G > 0; ++s) {
+    for (int i = 0; i < G; ++i) {
+      const int sg = c->glist[i];
+      const TermInfo& t = c->terms[c->sched_term[sg]];
+      const TermInfo& t1 = c->terms[c->sched_term[c->glist[(i + 1) % G]]];
+      const TermInfo& t2 = c->terms[c->sched_term[c->glist[(i + 2) % G]]];
+      const double theta = t.alpha * c->sched_mult[sg] * dtau;
+      std::memset(&gp, 0, sizeof(gp));
+      gp.ch = std::cosh(theta);
+      gp.sh = std::sinh(theta);
+      gp.nbits = nbits;
+      gp.w = (int)t.F.size();
+      gp.w1 = (int)t1.F.size();
+      gp.w2 = (int)t2.F.size();
+      for (int b : t.cbits) {
+        const int p = c->pos[b];
+        gp.cmask[p >> 6] |= 1ull << (p & 63);
+      }
+      gp.nsup = t.nsup;
+      gp.aQ = t.aQ & 3;
+      for (int j = 0; j < t.nsup; ++j) {
+        gp.px[j] = c->pos[t.sup[j]];
+        gp.pz[j] = c->pos[c->n + t.sup[j]];
+        gp.qx[j] = t.qx[j];
+        gp.qz[j] = t.qz[j];
+      }
+      for (int k = 0; k < gp.w; ++k)
+        if (c->pos[t.F[k]] != nbits - gp.w + k) return fail(c, ITPP_ERR_DEVICE, "internal error: rep invariant");
+      std::vector<int> pos1 = c->pos;
+      for (int m = 0; m < gp.w1; ++m) move_top(pos1, t1.F[m], nbits, &gp.mv[m]);
+      for (int b = 0; b < gp.w2; ++b) gp.fpos[b] = pos1[t2.F[b]];
+      gp.ov = 0;
+      for (int k = 0; k < gp.w1; ++k)
+        if (std::find(t.F.begin(), t.F.end(), t1.F[k]) != t.F.end()) gp.ov |= 1 << k;
+      gp.tile = tile;
+      gp.epoch = c->epoch;
+      c->epoch = (c->epoch + 1) & 0x3fffffffu;
+      if (c->epoch == 0) c->epoch = 1;
+      gp.delta = c->cfg.threshold;
+      gp.cap_elems = c->cap;
+      gp.status_cap = c->status_cap;
+      for (int b = 0; b < nbits; ++b) gp.pos_in[b] = (uint8_t)c->pos[b];
+      for (int b = 0; b < nbits; ++b) rp.pos[b] = (uint8_t)pos1[b];
+      const int in = c->cur, out = c->cur ^ 1;
+      const int pin = c->par, pout = c->par ^ 1;
+      HIP_TRY(c, launch_gate(c->NW, gp, c->side[in], c->side[out], c->plan + pin, c->plan + pout,
+                             c->filt + pin, c->ctl, c->status, grid, c->stream));
+      HIP_TRY(c, launch_select(c->NW, c->side[out], c->plan + pout, c->filt + pin, c->filt + pout,
+                               c->plan + pin, c->ctl, c->sel, rp, c->cfg.max_terms,
+                               c->cfg.cap_policy == ITPP_CAP_FAIL ? 1 : 0, sel_grid, c->stream));
+      c->pos.swap(pos1);
+      c->cur = out;
+      c->par = pout;
+    }
+  }
+  itpp_status s = check_error(c);
+  if (s != ITPP_OK) return s;
+  if (st) {
+    Ctl h{};
+    Filter f{};
+    HIP_TRY(c, hipMemcpyAsync(&h, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(&f, c->filt + c->par, sizeof(Filter), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    st->n_terms = (int64_t)f.n_survivors;
+    st->n_gates = (int64_t)(h.gates - g0);
+    st->term_updates = h.term_updates - tu0;
+    st->c_identity = f.cI;
+    st->cap_hit = (int32_t)h.cap_hit;
+  }
+  return ITPP_OK;
+}
+
+itpp_status itpp_num_terms(itpp_ctx c, int64_t* out) {
+  if (!c || !out) return ITPP_ERR_ARG;
+  if (!c->ready) return fail(c, ITPP_ERR_STATE, "no valid state (reset required)");
+  Filter f{};
+  HIP_TRY(c, hipMemcpyAsync(&f, c->filt + c->par, sizeof(Filter), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  *out = (int64_t)f.n_survivors;
+  return ITPP_OK;
+}
+
+itpp_status itpp_expect(itpp_ctx c, int32_t m, const uint64_t* x, const uint64_t* z, const double* coef,
+                        double* out) {
+  if (!c || !out) return ITPP_ERR_ARG;
+  if (m < 0 || (m > 0 && (!x || !z || !coef))) return fail(c, ITPP_ERR_ARG, "bad observable arrays");
+  if (!c->ready) return fail(c, ITPP_ERR_STATE, "no valid state (reset required)");
+  const int W = c->W;
+  for (int j = 0; j < m; ++j)
+    for (int q = 0; q < W; ++q) {
+      const int hi = c->n - 64 * q;
+      if (hi < 64) {
+        const uint64_t bad = hi <= 0 ? ~0ull : ~((1ull << hi) - 1ull);
+        if ((x[(size_t)j * W + q] | z[(size_t)j * W + q]) & bad)
+          return fail(c, ITPP_ERR_ARG, "observable has bits at or above n_qubits");
+      }
+    }
+  if (m == 0) {
+    *out = 0.0;
+    return ITPP_OK;
+  }
+  uint64_t *dx = nullptr, *dz = nullptr;
+  double* dc = nullptr;
+  HIP_TRY(c, hipMalloc(&dx, sizeof(uint64_t) * m * W));
+  HIP_TRY(c, hipMalloc(&dz, sizeof(uint64_t) * m * W));
+  HIP_TRY(c, hipMalloc(&dc, sizeof(double) * m));
+  hipMemcpyAsync(dx, x, sizeof(uint64_t) * m * W, hipMemcpyHostToDevice, c->stream);
+  hipMemcpyAsync(dz, z, sizeof(uint64_t) * m * W, hipMemcpyHostToDevice, c->stream);
+  hipMemcpyAsync(dc, coef, sizeof(double) * m, hipMemcpyHostToDevice, c->stream);
+  RepPos rp{};
+  rp.nbits = c->nbits;
+  for (int b = 0; b < c->nbits; ++b) rp.pos[b] = (uint8_t)c->pos[b];
+  hipError_t e = launch_observe(c->NW, c->side[c->cur], c->plan + c->par, c->filt + c->par, rp, dx, dz, dc, m,
+                                c->d_result, c->ctl, c->stream);
+  double r = 0.0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&r, c->d_result, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(dx);
+  (void)hipFree(dz);
+  (void)hipFree(dc);
+  if (e != hipSuccess) return hip_fail(c, e, "itpp_expect");
+  *out = r;
+  return ITPP_OK;
+}
+
+itpp_status itpp_export(itpp_ctx c, int64_t capacity, uint64_t* x, uint64_t* z, double* coef, int64_t* n_out) {
+  if (!c || !n_out) return ITPP_ERR_ARG;
+  if (!c->ready) return fail(c, ITPP_ERR_STATE, "no valid state (reset required)");
+  int64_t nt = 0;
+  itpp_status s = itpp_num_terms(c, &nt);
+  if (s != ITPP_OK) return s;
+  if (capacity < nt || !x || !z || !coef) {
+    *n_out = nt;
+    return fail(c, ITPP_ERR_ARG, "export capacity too small");
+  }
+  const int W = c->W;
+  uint64_t *dx = nullptr, *dz = nullptr;
+  double* dc = nullptr;
+  unsigned long long* dn = nullptr;
+  HIP_TRY(c, hipMalloc(&dx, sizeof(uint64_t) * std::max<int64_t>(nt, 1) * W));
+  HIP_TRY(c, hipMalloc(&dz, sizeof(uint64_t) * std::max<int64_t>(nt, 1) * W));
+  HIP_TRY(c, hipMalloc(&dc, sizeof(double) * std::max<int64_t>(nt, 1)));
+  HIP_TRY(c, hipMalloc(&dn, sizeof(unsigned long long)));
+  hipMemsetAsync(dn, 0, sizeof(unsigned long long), c->stream);
+  RepPos rp{};
+  rp.nbits = c->nbits;
+  for (int b = 0; b < c->nbits; ++b) rp.pos[b] = (uint8_t)c->pos[b];
+  hipError_t e = launch_export(c->NW, c->side[c->cur], c->plan + c->par, c->filt + c->par, rp, dx, dz, dc, dn,
+                               (uint64_t)nt, c->cus * 4, c->stream);
+  unsigned long long cnt = 0;
+  std::vector<uint64_t> hx((size_t)nt * W), hz((size_t)nt * W);
+  std::vector<double> hc(nt);
+  if (e == hipSuccess) e = hipMemcpyAsync(&cnt, dn, sizeof(cnt), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && nt > 0) e = hipMemcpyAsync(hx.data(), dx, sizeof(uint64_t) * nt * W, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && nt > 0) e = hipMemcpyAsync(hz.data(), dz, sizeof(uint64_t) * nt * W, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && nt > 0) e = hipMemcpyAsync(hc.data(), dc, sizeof(double) * nt, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(dx);
+  (void)hipFree(dz);
+  (void)hipFree(dc);
+  (void)hipFree(dn);
+  if (e != hipSuccess) return hip_fail(c, e, "itpp_export");
+  if ((int64_t)cnt != nt) return fail(c, ITPP_ERR_DEVICE, "internal error: export count mismatch");
+  std::vector<int64_t> order(nt);
+  for (int64_t i = 0; i < nt; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    for (int q = W - 1; q >= 0; --q)
+      if (hx[a * W + q] != hx[b * W + q]) return hx[a * W + q] < hx[b * W + q];
+    for (int q = W - 1; q >= 0; --q)
+      if (hz[a * W + q] != hz[b * W + q]) return hz[a * W + q] < hz[b * W + q];
+    return false;
+  });
+  for (int64_t i = 0; i < nt; ++i) {
+    for (int q = 0; q < W; ++q) {
+      x[i * W + q] = hx[order[i] * W + q];
+      z[i * W + q] = hz[order[i] * W + q];
+    }
+    coef[i] = hc[order[i]];
+  }
+  *n_out = nt;
+  return ITPP_OK;
+}
+
+}  // extern "C"

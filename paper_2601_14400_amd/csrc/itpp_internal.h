@@ -1,0 +1,152 @@
+// Internal structures shared by the ITPP kernels and the host runtime.
+//
+// State layout in HBM (one "side" of a ping-pong pair):
+//   key words  kw[0..NW-1][cap]   (structure of arrays, NW = 2W uint64 words)
+//   coef       coef[cap]          (double, value before normalisation)
+// Keys are stored in a bit-permuted representation ("rep"): the 2n x/z bits
+// of a string are placed at positions chosen by the host so that the bits
+// flipped by the NEXT gate are the most significant ones.  Numeric order of
+// rep keys is then a lexicographic bit order in which the strings of equal
+// flip-bit pattern ("class") are contiguous, and xor with the gate string
+// only changes the class.  The pairing P <-> Q P of Eq. (ITPP_PropRules)
+// becomes a merge-join of class c with class ~c.
+//
+// A stored state is a set of regions (c, e): c = class under the gate that
+// produced it, e = class under the gate that will read it.  The reader sees
+// its class e as the concatenation over c of regions (c, e), which is sorted.
+#pragma once
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+namespace itpp {
+
+constexpr int kMaxClassBits = 2;            // a gate may flip at most two key bits
+constexpr int kMaxClasses = 1 << kMaxClassBits;
+constexpr int kMaxWords = 2;                 // W <= 2  (n <= 128)
+constexpr int kMaxKeyWords = 2 * kMaxWords;  // NW <= 4
+constexpr int kMaxBits = 64 * kMaxKeyWords;  // 256
+constexpr int kHistBins = 1024;              // |c| histogram: 16 bins per octave
+constexpr int kHistShift = 48;               // bits >> 48: 11 exponent + 4 mantissa bits
+constexpr uint32_t kHistBase = (1023u - 62u) << 4;  // bin 0 starts at 2^-62
+
+// Description of a stored state (written by the gate that produced it).
+struct Plan {
+  uint32_t cnt[kMaxClasses][kMaxClasses];   // elements written in region (c, e)
+  uint64_t base[kMaxClasses][kMaxClasses];  // first element of region (c, e)
+  uint32_t ncnt[kMaxClasses][kMaxClasses];  // stored elements of class e with pattern f of the gate after
+  int32_t wc;                               // class bits of the producer (c)
+  int32_t we;                               // class bits of the reader (e)
+  uint32_t pad[2];
+};
+
+// Truncation / normalisation decided after a gate, applied when the next
+// gate (or a readout) loads the stored elements.
+struct Filter {
+  double cI;                 // identity coefficient before normalisation
+  uint64_t kth_bits;         // |c| bit pattern of the (K-1)-th largest non-identity
+  uint32_t cap_active;       // 1: elements below kth_bits are dropped
+  uint32_t tie_active;       // 1: elements equal to kth_bits are kept only up to tie_key
+  uint64_t tie_key[kMaxKeyWords];  // canonical key (x words, then z words) of the last tied survivor
+  uint64_t n_written;        // stored elements (identity included)
+  uint64_t n_survivors;      // elements that pass the filter
+};
+
+// Per-run control block (device).
+struct Ctl {
+  uint32_t ticket;           // tile ticket of the running gate
+  uint32_t error;            // sticky error code (see kErr*)
+  uint64_t n_written_nonid;  // written non-identity outputs of the running gate
+  double cI_out;             // identity output of the running gate
+  uint32_t have_cI;
+  uint32_t hist[kHistBins];
+  // selection scratch
+  uint32_t sel_bin;
+  uint32_t sel_need;         // elements still needed from sel_bin
+  uint64_t cand_count;
+  double term_updates;
+  uint64_t gates;
+  uint32_t cap_hit;
+  uint32_t pad;
+};
+
+enum : uint32_t {
+  kErrNone = 0,
+  kErrNumeric = 1,     // identity coefficient not finite / not positive
+  kErrCapacity = 2,    // a buffer bound was exceeded (library bug or bad sizing)
+  kErrSpin = 3,        // a look-back wait exceeded its bound
+  kErrCap = 4,         // cap reached under the FAIL policy
+  kErrPhase = 5,       // commuting strings gave an imaginary phase
+};
+
+// Lookback record of one tile: two sides x kMaxClasses counters.
+struct TileStatus {
+  uint32_t flag;                      // (epoch << 2) | state, state 1 = aggregate, 2 = inclusive
+  uint32_t agg[2 * kMaxClasses];
+  uint32_t incl[2 * kMaxClasses];
+  uint32_t pad[3];
+};
+
+// Device arrays of one side of the ping-pong state buffers.
+struct Side {
+  uint64_t* kw[kMaxKeyWords];
+  double* coef;
+};
+
+// Rep positions of the canonical bits of a stored state.
+struct RepPos {
+  uint8_t pos[kMaxBits];
+  int32_t nbits;
+  int32_t pad;
+};
+
+// Parameters of one elementary gate, computed on the host.
+struct GateParams {
+  double ch, sh;             // cosh(theta), sinh(theta)
+  int32_t nbits;             // 2n: meaningful rep bits
+  int32_t w;                 // class bits of this gate (1 or 2)
+  int32_t w1;                // class bits of the next gate
+  int32_t w2;                // class bits of the gate after next
+  uint64_t cmask[kMaxKeyWords];  // rep positions whose parity marks anticommutation
+  // phase of Q P for commuting P: qubits in the support of Q
+  int32_t nsup;
+  int32_t aQ;                // number of Y letters in Q (mod 4)
+  int32_t px[2], pz[2];      // rep positions of x_j, z_j
+  int32_t qx[2], qz[2];      // letters of Q on those qubits
+  int32_t mv[kMaxClassBits];     // rep positions (sequential) moved to the top for the next gate
+  int32_t fpos[kMaxClassBits];   // positions, in the next rep, of the bits of the gate after next
+  int32_t ov;                // pattern over the next gate's bits flipped by this gate
+  int32_t tile;              // merged elements per tile
+  uint32_t epoch;            // unique per launched gate (look-back tags)
+  uint32_t check_write_threshold;
+  double delta;              // keep |c| > delta
+  uint64_t cap_elems;        // capacity of each side in elements
+  uint64_t status_cap;       // entries of the look-back status array
+  uint8_t pos_in[kMaxBits];  // canonical bit -> rep position of the stored (input) keys
+};
+
+// Selection scratch (device): candidates of the K-th value and tied keys.
+struct SelBuf {
+  uint64_t* cand_bits;
+  uint64_t* cand_idx;
+  uint64_t* tie_keys;   // kMaxKeyWords words per tied element
+  uint64_t cap;         // capacity of each array in elements
+};
+
+// Host launchers (defined in itpp_kernels.hip).
+hipError_t launch_init(int nw, Side s0, Plan* plan, Filter* filt, Ctl* ctl, int w0, hipStream_t st);
+hipError_t launch_gate(int nw, const GateParams& gp, Side in, Side out, const Plan* plan_in,
+                       Plan* plan_out, const Filter* filt_in, Ctl* ctl, TileStatus* status, int grid,
+                       hipStream_t st);
+hipError_t launch_select(int nw, Side out, const Plan* plan_out, const Filter* filt_in,
+                         Filter* filt_out, Plan* plan_next, Ctl* ctl, SelBuf sel, const RepPos& rp,
+                         int64_t K, int cap_fail, int grid, hipStream_t st);
+hipError_t launch_observe(int nw, Side s, const Plan* plan, const Filter* filt, const RepPos& rp,
+                          const uint64_t* ox, const uint64_t* oz, const double* oc, int32_t m,
+                          double* result, Ctl* ctl, hipStream_t st);
+hipError_t launch_export(int nw, Side s, const Plan* plan, const Filter* filt, const RepPos& rp,
+                         uint64_t* ex, uint64_t* ez, double* ec, unsigned long long* count,
+                         uint64_t limit, int grid, hipStream_t st);
+int gate_tile(int nw);
+
+}  // namespace itpp
