@@ -78,7 +78,19 @@ typedef struct {
   double c_identity;     /* identity coefficient before the last normalisation */
   int32_t cap_hit;       /* 1 if the cap truncated at least one gate */
   int32_t reserved0;
+  double alg_bytes;      /* sum over gates of (strings in + strings out) * (16W + 8) */
 } itpp_stats;
+
+/* Kernel timing gathered with HIP events on the context's stream while
+ * enabled (itpp_set_timing): total milliseconds and launch counts of the
+ * gate kernel and of the truncation-selection kernels, and the algorithmic
+ * bytes of the timed gates (strings in + strings out times 16W + 8). */
+typedef struct {
+  double gate_ms;
+  double select_ms;
+  int64_t gate_launches;
+  double alg_bytes;
+} itpp_timing;
 
 /* Create a context on the current HIP device.  Validation (ITPP_ERR_ARG):
  * n_qubits outside 1..128, threshold negative, not finite or >= 1,
@@ -111,10 +123,17 @@ itpp_status itpp_reset(itpp_ctx ctx);
 /* Apply n_steps Trotter steps of the schedule with step dtau > 0 (finite).
  * Runs asynchronously on cfg.stream except for the final status check; st
  * (nullable) receives the statistics of this call.  ITPP_ERR_CAP under
- * ITPP_CAP_FAIL when a gate leaves more than max_terms strings (the state is
- * then that of the last completed gate); ITPP_ERR_NUMERIC if the identity
- * coefficient is not finite and positive. */
+ * ITPP_CAP_FAIL when a gate leaves more than max_terms strings;
+ * ITPP_ERR_NUMERIC if the identity coefficient is not finite and positive.
+ * After either error the state is invalid until itpp_reset. */
 itpp_status itpp_evolve(itpp_ctx ctx, double dtau, int64_t n_steps, itpp_stats* st);
+
+/* Apply the next n_gates elementary gates of the schedule (continuing
+ * inside a Trotter step if the previous call stopped there); same semantics
+ * and errors as itpp_evolve, which applies n_steps times the schedule's
+ * non-identity gates.  Lets a caller inspect or checkpoint the state after
+ * any elementary gate of Algorithm 1. */
+itpp_status itpp_evolve_gates(itpp_ctx ctx, double dtau, int64_t n_gates, itpp_stats* st);
 
 /* <O> = sum_j coef[j] * a_{P_j} for O = sum_j coef[j] P_j (Eq.
  * Expectation_Value in the Pauli basis; absent strings count 0), summed in
@@ -132,7 +151,15 @@ itpp_status itpp_num_terms(itpp_ctx ctx, int64_t* out);
 itpp_status itpp_export(itpp_ctx ctx, int64_t capacity, uint64_t* x, uint64_t* z, double* coef,
                         int64_t* n_out);
 
-/* Message for the last error on ctx (static string for ctx == NULL). */
+/* Enable (1) or disable (0) per-gate HIP event timing; enabling clears the
+ * accumulated figures.  Timing adds two event records per gate. */
+itpp_status itpp_set_timing(itpp_ctx ctx, int32_t enable);
+
+/* Wait for the stream and return the accumulated timing. */
+itpp_status itpp_get_timing(itpp_ctx ctx, itpp_timing* out);
+
+/* Message for the last error on ctx (for ctx == NULL: the last itpp_create
+ * failure of this thread). */
 const char* itpp_last_error(itpp_ctx ctx);
 
 /* Library build information ("gfx950 ..."). */

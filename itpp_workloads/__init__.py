@@ -260,3 +260,40 @@ def random_pauli_strings(n: int, count: int, seed: int, density: float = 0.5) ->
                 s.append("I")
         out.append("".join(s))
     return out
+
+
+def random_two_flip_hamiltonian(n: int, n_terms: int, seed: int, span: int = 4) -> Tuple[List[str], List[float]]:
+    """Random terms that flip at most two x/z bits: single-site X, Y, Z and
+    two-site products of X and Z letters within ``span`` neighbouring qubits
+    (periodic)."""
+    rng = np.random.default_rng(seed)
+    strings: List[str] = []
+    alphas: List[float] = []
+    seen = set()
+    while len(strings) < n_terms:
+        s = ["I"] * n
+        i = int(rng.integers(0, n))
+        if rng.random() < 0.4:
+            s[i] = "XYZ"[int(rng.integers(0, 3))]
+        else:
+            j = (i + int(rng.integers(1, max(2, min(span, n))))) % n
+            if j == i:
+                continue
+            s[i] = "XZ"[int(rng.integers(0, 2))]
+            s[j] = "XZ"[int(rng.integers(0, 2))]
+        key = "".join(s)
+        if key in seen:
+            continue
+        seen.add(key)
+        strings.append(key)
+        alphas.append(float(rng.uniform(-1.0, 1.0)))
+    return strings, alphas
+
+
+def random_two_flip_workload(name: str, n: int, n_terms: int, seed: int, dtau: float, n_steps: int,
+                             delta: float, K: int) -> Workload:
+    strings, alphas = random_two_flip_hamiltonian(n, n_terms, seed)
+    sched = [(k, 1.0) for k in range(n_terms)]
+    return Workload(name=name, n=n, strings=strings, alphas=alphas, schedule=sched, dtau=dtau,
+                    n_steps=n_steps, delta=delta, K=K, observables={"energy": (list(strings), list(alphas))},
+                    meta=dict(model="random_two_flip", seed=seed))

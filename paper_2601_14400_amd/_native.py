@@ -21,8 +21,8 @@ STATUS = {0: "ITPP_OK", 1: "ITPP_ERR_ARG", 2: "ITPP_ERR_OOM", 3: "ITPP_ERR_CAP",
 
 # Every entry point declared in include/itpp.h.
 EXPORTED = ["itpp_create", "itpp_destroy", "itpp_set_hamiltonian", "itpp_set_schedule",
-            "itpp_reset", "itpp_evolve", "itpp_expect", "itpp_num_terms", "itpp_export",
-            "itpp_last_error", "itpp_version"]
+            "itpp_reset", "itpp_evolve", "itpp_evolve_gates", "itpp_expect", "itpp_num_terms", "itpp_export",
+            "itpp_set_timing", "itpp_get_timing", "itpp_last_error", "itpp_version"]
 
 
 class ItppConfig(ctypes.Structure):
@@ -35,7 +35,13 @@ class ItppConfig(ctypes.Structure):
 class ItppStats(ctypes.Structure):
     _fields_ = [("n_terms", ctypes.c_int64), ("n_gates", ctypes.c_int64),
                 ("term_updates", ctypes.c_double), ("c_identity", ctypes.c_double),
-                ("cap_hit", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+                ("cap_hit", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("alg_bytes", ctypes.c_double)]
+
+
+class ItppTiming(ctypes.Structure):
+    _fields_ = [("gate_ms", ctypes.c_double), ("select_ms", ctypes.c_double),
+                ("gate_launches", ctypes.c_int64), ("alg_bytes", ctypes.c_double)]
 
 
 class ItppError(RuntimeError):
@@ -70,9 +76,12 @@ def load_library(path: Optional[str] = None):
     lib.itpp_set_schedule.argtypes = [vp, i32, vp, vp]
     lib.itpp_reset.argtypes = [vp]
     lib.itpp_evolve.argtypes = [vp, dbl, i64, ctypes.POINTER(ItppStats)]
+    lib.itpp_evolve_gates.argtypes = [vp, dbl, i64, ctypes.POINTER(ItppStats)]
     lib.itpp_expect.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(dbl)]
     lib.itpp_num_terms.argtypes = [vp, ctypes.POINTER(i64)]
     lib.itpp_export.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(i64)]
+    lib.itpp_set_timing.argtypes = [vp, i32]
+    lib.itpp_get_timing.argtypes = [vp, ctypes.POINTER(ItppTiming)]
     lib.itpp_last_error.argtypes = [vp]
     lib.itpp_last_error.restype = ctypes.c_char_p
     lib.itpp_version.restype = ctypes.c_char_p
@@ -184,8 +193,26 @@ class Engine:
     def evolve(self, dtau: float, n_steps: int) -> Dict[str, float]:
         st = ItppStats()
         self._check(self._lib.itpp_evolve(self._h, float(dtau), int(n_steps), ctypes.byref(st)))
+        return self._stats(st)
+
+    def evolve_gates(self, dtau: float, n_gates: int) -> Dict[str, float]:
+        st = ItppStats()
+        self._check(self._lib.itpp_evolve_gates(self._h, float(dtau), int(n_gates), ctypes.byref(st)))
+        return self._stats(st)
+
+    @staticmethod
+    def _stats(st):
         return {"n_terms": st.n_terms, "n_gates": st.n_gates, "term_updates": st.term_updates,
-                "c_identity": st.c_identity, "cap_hit": st.cap_hit}
+                "c_identity": st.c_identity, "cap_hit": st.cap_hit, "alg_bytes": st.alg_bytes}
+
+    def set_timing(self, enable: bool = True):
+        self._check(self._lib.itpp_set_timing(self._h, 1 if enable else 0))
+
+    def timing(self) -> Dict[str, float]:
+        t = ItppTiming()
+        self._check(self._lib.itpp_get_timing(self._h, ctypes.byref(t)))
+        return {"gate_ms": t.gate_ms, "select_ms": t.select_ms, "gate_launches": t.gate_launches,
+                "alg_bytes": t.alg_bytes}
 
     def expect(self, strings: Sequence[str], coefs: Sequence[float]) -> float:
         x, z = strings_to_words(strings, self.n)

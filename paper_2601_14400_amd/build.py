@@ -18,6 +18,9 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-ffp-contract=off", "-fno-fast-math",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep per-thread arrays in registers instead of moving them to LDS,
+    # which would cut the gate kernel's occupancy
+    "-mllvm", "-disable-promote-alloca-to-lds",
 ]
 
 

@@ -50,6 +50,7 @@ struct itpp_ctx_s {
   Ctl* ctl = nullptr;
   TileStatus* status = nullptr;
   uint64_t status_cap = 0;
+  uint64_t* part = nullptr;  // merge-path boundaries (2 words each)
   SelBuf sel{};
   double* d_result = nullptr;
   std::vector<void*> allocs;
@@ -61,10 +62,17 @@ struct itpp_ctx_s {
   // state
   std::vector<int> pos;  // canonical bit -> rep position of the stored state
   int cur = 0;           // side holding the stored state
+  int gpos = 0;          // index in glist of the next gate to apply
   int par = 0;           // plan/filter slot describing the stored state
   bool ready = false;
   uint32_t epoch = 1;
   std::string err;
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev;  // pool: 3 events per timed gate
+  size_t ev_used = 0;
+  double t_gate_ms = 0.0, t_sel_ms = 0.0, t_alg_bytes = 0.0;
+  int64_t t_gates = 0;
 };
 
 namespace {
@@ -109,6 +117,39 @@ int popcount_words(const std::vector<uint64_t>& v) {
 void free_all(itpp_ctx c) {
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  c->ev.clear();
+  c->ev_used = 0;
+}
+
+hipError_t next_event(itpp_ctx c, hipEvent_t* e) {
+  if (c->ev_used == c->ev.size()) {
+    hipEvent_t x;
+    hipError_t r = hipEventCreate(&x);
+    if (r != hipSuccess) return r;
+    c->ev.push_back(x);
+  }
+  *e = c->ev[c->ev_used++];
+  return hipSuccess;
+}
+
+// Sum the elapsed times of the recorded event triples and recycle the pool.
+hipError_t drain_events(itpp_ctx c) {
+  if (c->ev_used == 0) return hipSuccess;
+  hipError_t r = hipStreamSynchronize(c->stream);
+  if (r != hipSuccess) return r;
+  for (size_t i = 0; i + 2 < c->ev_used; i += 3) {
+    float a = 0.f, b = 0.f;
+    r = hipEventElapsedTime(&a, c->ev[i], c->ev[i + 1]);
+    if (r != hipSuccess) return r;
+    r = hipEventElapsedTime(&b, c->ev[i + 1], c->ev[i + 2]);
+    if (r != hipSuccess) return r;
+    c->t_gate_ms += a;
+    c->t_sel_ms += b;
+    c->t_gates += 1;
+  }
+  c->ev_used = 0;
+  return hipSuccess;
 }
 
 template <typename T>
@@ -138,6 +179,7 @@ itpp_status do_reset(itpp_ctx c) {
   if (!c->glist.empty()) w0 = (int)c->terms[c->sched_term[c->glist[0]]].F.size();
   c->cur = 0;
   c->par = 0;
+  c->gpos = 0;
   HIP_TRY(c, launch_init(c->NW, c->side[0], c->plan + 0, c->filt + 0, c->ctl, w0, c->stream));
   c->ready = true;
   return ITPP_OK;
@@ -233,6 +275,7 @@ itpp_status itpp_create(const itpp_config* cfg, itpp_ctx* out) {
   if (ok) ok = dalloc(c, &c->filt, 2) == hipSuccess;
   if (ok) ok = dalloc(c, &c->ctl, 1) == hipSuccess;
   if (ok) ok = dalloc(c, &c->status, c->status_cap) == hipSuccess;
+  if (ok) ok = dalloc(c, &c->part, 2 * (c->status_cap + kMaxClasses + 4)) == hipSuccess;
   if (ok) ok = dalloc(c, &c->sel.cand_bits, sel_cap) == hipSuccess;
   if (ok) ok = dalloc(c, &c->sel.cand_idx, sel_cap) == hipSuccess;
   if (ok) ok = dalloc(c, &c->sel.tie_keys, sel_cap * c->NW) == hipSuccess;
@@ -341,11 +384,25 @@ itpp_status itpp_reset(itpp_ctx c) {
   return do_reset(c);
 }
 
+static itpp_status run_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stats* st);
+
 itpp_status itpp_evolve(itpp_ctx c, double dtau, int64_t n_steps, itpp_stats* st) {
   if (!c) return ITPP_ERR_ARG;
   if (c->sched_term.empty()) return fail(c, ITPP_ERR_STATE, "set_schedule first");
   if (!(dtau > 0.0) || !std::isfinite(dtau)) return fail(c, ITPP_ERR_ARG, "dtau must be finite and > 0");
   if (n_steps < 0) return fail(c, ITPP_ERR_ARG, "n_steps must be >= 0");
+  return run_gates(c, dtau, n_steps * (int64_t)c->glist.size(), st);
+}
+
+itpp_status itpp_evolve_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stats* st) {
+  if (!c) return ITPP_ERR_ARG;
+  if (c->sched_term.empty()) return fail(c, ITPP_ERR_STATE, "set_schedule first");
+  if (!(dtau > 0.0) || !std::isfinite(dtau)) return fail(c, ITPP_ERR_ARG, "dtau must be finite and > 0");
+  if (n_gates < 0) return fail(c, ITPP_ERR_ARG, "n_gates must be >= 0");
+  return run_gates(c, dtau, n_gates, st);
+}
+
+static itpp_status run_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stats* st) {
   if (!c->ready) {
     itpp_status s = do_reset(c);
     if (s != ITPP_OK) return s;
@@ -356,17 +413,19 @@ itpp_status itpp_evolve(itpp_ctx c, double dtau, int64_t n_steps, itpp_stats* st
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (h0.error) return check_error(c);
   const double tu0 = h0.term_updates;
+  const double ae0 = h0.alg_elems;
   const uint64_t g0 = h0.gates;
   const int G = (int)c->glist.size();
-  const int grid = c->cus * 3;
+  const int grid = c->cus * 2;
   const int sel_grid = c->cus * 4;
   const int tile = gate_tile(c->NW);
   const int nbits = c->nbits;
   GateParams gp{};
   RepPos rp{};
   rp.nbits = nbits;
-  for (int64_t s = 0; s < n_steps && G > 0; ++s) {
-    for (int i = 0; i < G; ++i) {
+  for (int64_t gi = 0; gi < n_gates && G > 0; ++gi) {
+    {
+      const int i = c->gpos;
       const int sg = c->glist[i];
       const TermInfo& t = c->terms[c->sched_term[sg]];
       const TermInfo& t1 = c->terms[c->sched_term[c->glist[(i + 1) % G]]];
@@ -410,14 +469,25 @@ itpp_status itpp_evolve(itpp_ctx c, double dtau, int64_t n_steps, itpp_stats* st
       for (int b = 0; b < nbits; ++b) rp.pos[b] = (uint8_t)pos1[b];
       const int in = c->cur, out = c->cur ^ 1;
       const int pin = c->par, pout = c->par ^ 1;
+      hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+      if (c->timing) {
+        if (c->ev_used + 3 > 3 * 4096) HIP_TRY(c, drain_events(c));
+        HIP_TRY(c, next_event(c, &e0));
+        HIP_TRY(c, next_event(c, &e1));
+        HIP_TRY(c, next_event(c, &e2));
+        HIP_TRY(c, hipEventRecord(e0, c->stream));
+      }
       HIP_TRY(c, launch_gate(c->NW, gp, c->side[in], c->side[out], c->plan + pin, c->plan + pout,
-                             c->filt + pin, c->ctl, c->status, grid, c->stream));
+                             c->filt + pin, c->ctl, c->status, c->part, grid, c->stream));
+      if (c->timing) HIP_TRY(c, hipEventRecord(e1, c->stream));
       HIP_TRY(c, launch_select(c->NW, c->side[out], c->plan + pout, c->filt + pin, c->filt + pout,
                                c->plan + pin, c->ctl, c->sel, rp, c->cfg.max_terms,
                                c->cfg.cap_policy == ITPP_CAP_FAIL ? 1 : 0, sel_grid, c->stream));
+      if (c->timing) HIP_TRY(c, hipEventRecord(e2, c->stream));
       c->pos.swap(pos1);
       c->cur = out;
       c->par = pout;
+      c->gpos = (i + 1) % G;
     }
   }
   itpp_status s = check_error(c);
@@ -433,7 +503,33 @@ itpp_status itpp_evolve(itpp_ctx c, double dtau, int64_t n_steps, itpp_stats* st
     st->term_updates = h.term_updates - tu0;
     st->c_identity = f.cI;
     st->cap_hit = (int32_t)h.cap_hit;
+    st->alg_bytes = (h.alg_elems - ae0) * (double)(8 * c->NW + 8);
   }
+  if (c->timing) {
+    Ctl h{};
+    HIP_TRY(c, hipMemcpyAsync(&h, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->t_alg_bytes += (h.alg_elems - ae0) * (double)(8 * c->NW + 8);
+  }
+  return ITPP_OK;
+}
+
+itpp_status itpp_set_timing(itpp_ctx c, int32_t enable) {
+  if (!c) return ITPP_ERR_ARG;
+  HIP_TRY(c, drain_events(c));
+  c->timing = enable != 0;
+  c->t_gate_ms = c->t_sel_ms = c->t_alg_bytes = 0.0;
+  c->t_gates = 0;
+  return ITPP_OK;
+}
+
+itpp_status itpp_get_timing(itpp_ctx c, itpp_timing* out) {
+  if (!c || !out) return ITPP_ERR_ARG;
+  HIP_TRY(c, drain_events(c));
+  out->gate_ms = c->t_gate_ms;
+  out->select_ms = c->t_sel_ms;
+  out->gate_launches = c->t_gates;
+  out->alg_bytes = c->t_alg_bytes;
   return ITPP_OK;
 }
 

@@ -29,6 +29,9 @@ constexpr int kMaxBits = 64 * kMaxKeyWords;  // 256
 constexpr int kHistBins = 1024;              // |c| histogram: 16 bins per octave
 constexpr int kHistShift = 48;               // bits >> 48: 11 exponent + 4 mantissa bits
 constexpr uint32_t kHistBase = (1023u - 62u) << 4;  // bin 0 starts at 2^-62
+constexpr int kFineBins = 1024;              // fine |c| histogram around the predicted K-th value
+constexpr int kFineShift = 38;               // bin width 2^38 ulps of the f64 pattern
+constexpr uint64_t kFineHalf = 1ull << 47;   // window half width (~2.2% relative)
 
 // Description of a stored state (written by the gate that produced it).
 struct Plan {
@@ -60,11 +63,15 @@ struct Ctl {
   double cI_out;             // identity output of the running gate
   uint32_t have_cI;
   uint32_t hist[kHistBins];
+  uint32_t fhist[kFineBins];
+  uint64_t n_above_hi;       // written non-identity outputs above the fine window
   // selection scratch
-  uint32_t sel_bin;
-  uint32_t sel_need;         // elements still needed from sel_bin
+  uint64_t sel_lo, sel_hi;   // |c| bit range that holds the K-th value
+  uint32_t sel_need;         // elements still needed from that range
+  uint32_t pad2;
   uint64_t cand_count;
   double term_updates;
+  double alg_elems;          // sum over gates of survivors in + survivors out
   uint64_t gates;
   uint32_t cap_hit;
   uint32_t pad;
@@ -79,12 +86,12 @@ enum : uint32_t {
   kErrPhase = 5,       // commuting strings gave an imaginary phase
 };
 
-// Lookback record of one tile: two sides x kMaxClasses counters.
+// Look-back record of one tile: words [0, 2C) hold the tile's aggregate
+// counts, words [2C, 4C) its inclusive prefix (C = kMaxClasses; two output
+// streams per tile).  Each word is (epoch << 32) | count, so a single atomic
+// load both validates and reads a counter.
 struct TileStatus {
-  uint32_t flag;                      // (epoch << 2) | state, state 1 = aggregate, 2 = inclusive
-  uint32_t agg[2 * kMaxClasses];
-  uint32_t incl[2 * kMaxClasses];
-  uint32_t pad[3];
+  unsigned long long w[4 * kMaxClasses];
 };
 
 // Device arrays of one side of the ping-pong state buffers.
@@ -136,8 +143,8 @@ struct SelBuf {
 // Host launchers (defined in itpp_kernels.hip).
 hipError_t launch_init(int nw, Side s0, Plan* plan, Filter* filt, Ctl* ctl, int w0, hipStream_t st);
 hipError_t launch_gate(int nw, const GateParams& gp, Side in, Side out, const Plan* plan_in,
-                       Plan* plan_out, const Filter* filt_in, Ctl* ctl, TileStatus* status, int grid,
-                       hipStream_t st);
+                       Plan* plan_out, const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part,
+                       int grid, hipStream_t st);
 hipError_t launch_select(int nw, Side out, const Plan* plan_out, const Filter* filt_in,
                          Filter* filt_out, Plan* plan_next, Ctl* ctl, SelBuf sel, const RepPos& rp,
                          int64_t K, int cap_fail, int grid, hipStream_t st);

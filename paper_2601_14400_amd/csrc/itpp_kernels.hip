@@ -61,14 +61,32 @@ __device__ __forceinline__ bool key_zero(const Key<NW>& a) {
   return o == 0;
 }
 
+// Bit access at a runtime position without indexing the register array
+// (a dynamic index would move the key to scratch memory).
+template <int NW>
+__device__ __forceinline__ uint64_t word_at(const Key<NW>& k, int wi) {
+  uint64_t v = k.w[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) v = (wi == i) ? k.w[i] : v;
+  return v;
+}
+
 template <int NW>
 __device__ __forceinline__ int get_bit(const Key<NW>& k, int p) {
-  return (int)((k.w[p >> 6] >> (p & 63)) & 1ull);
+  return (int)((word_at(k, p >> 6) >> (p & 63)) & 1ull);
+}
+
+template <int NW>
+__device__ __forceinline__ void xor_bit(Key<NW>& k, int p, uint64_t v) {
+  const int wi = p >> 6;
+  const uint64_t m = v << (p & 63);
+#pragma unroll
+  for (int i = 0; i < NW; ++i) k.w[i] ^= (wi == i) ? m : 0ull;
 }
 
 template <int NW>
 __device__ __forceinline__ void flip_bit(Key<NW>& k, int p) {
-  k.w[p >> 6] ^= (1ull << (p & 63));
+  xor_bit(k, p, 1ull);
 }
 
 // Flip the w most significant meaningful bits (the bits the gate flips).
@@ -89,7 +107,7 @@ __device__ __forceinline__ int class_of(const Key<NW>& k, int nbits, int w) {
 // Move the bit at position p to position nbits-1; bits above p shift down.
 template <int NW>
 __device__ __forceinline__ Key<NW> move_top(const Key<NW>& k, int p, int nbits) {
-  const int b = get_bit(k, p);
+  const uint64_t b = (uint64_t)get_bit(k, p);
   Key<NW> r;
 #pragma unroll
   for (int i = 0; i < NW; ++i) {
@@ -104,7 +122,7 @@ __device__ __forceinline__ Key<NW> move_top(const Key<NW>& k, int p, int nbits) 
       lm = (1ull << (p - lo)) - 1ull;
     r.w[i] = (k.w[i] & lm) | (shr & ~lm);
   }
-  if (b) r.w[(nbits - 1) >> 6] |= 1ull << ((nbits - 1) & 63);
+  xor_bit(r, nbits - 1, b);  // bit nbits-1 of the shifted key is zero
   return r;
 }
 
@@ -134,7 +152,7 @@ __device__ inline Key<NW> to_canonical(const Key<NW>& k, const uint8_t* pos, int
     if (get_bit(k, pos[cb])) {
       const int word = (cb < n) ? (cb >> 6) : (W + ((cb - n) >> 6));
       const int bit = (cb < n) ? (cb & 63) : ((cb - n) & 63);
-      c.w[word] |= 1ull << bit;
+      xor_bit(c, 64 * word + bit, 1ull);
     }
   }
   return c;
@@ -193,7 +211,8 @@ struct ClassView {
   }
 };
 
-__device__ inline ClassView make_view(const Plan& p, int cls) {
+__device__ inline ClassView make_view(const Plan* __restrict__ pp, int cls) {
+  const Plan& p = *pp;
   ClassView v;
   const int nc = 1 << p.wc;
   v.nseg = nc;
@@ -208,7 +227,9 @@ __device__ inline ClassView make_view(const Plan& p, int cls) {
     }
   }
   v.start[kMaxClasses] = acc;
-  if (nc < kMaxClasses) v.start[nc] = acc;
+#pragma unroll
+  for (int c = 1; c < kMaxClasses; ++c)
+    if (c >= nc) v.start[c] = acc;
   return v;
 }
 
@@ -278,90 +299,224 @@ __device__ inline void block_scan2(uint64_t& a, uint64_t& b, uint64_t* wa, uint6
   __syncthreads();
 }
 
-// End (exclusive) of output region (c, e): the next region's base in the
-// (c major, e minor) layout, or the total for the last region.
-__device__ __forceinline__ uint64_t region_end(const uint64_t (*ob)[kMaxClasses], int c, int e, int ncls,
-                                               int ncls1) {
-  (void)ncls;
-  (void)ncls1;
+// End (exclusive) of output region (c, e) in the (c major, e minor) layout.
+__device__ __forceinline__ uint64_t region_end(const uint64_t (*ob)[kMaxClasses], int c, int e) {
   int cc = c, ee = e + 1;
   if (ee == kMaxClasses) {
     ee = 0;
     ++cc;
   }
-  if (cc == kMaxClasses) return ob[kMaxClasses][0];
   return ob[cc][ee];
 }
 
+// Join layout shared by the partition and gate kernels: the classes of the
+// gate's input, and for join j (classes j and ~j) its first tile and first
+// boundary index.
+struct JoinLayout {
+  ClassView views[kMaxClasses];
+  uint64_t tiles_before[kMaxClasses / 2 + 1];
+  int njoin, full;
+};
+
+__device__ inline void make_layout(JoinLayout& L, const Plan* __restrict__ pin, int w, int tile) {
+  const int ncls = 1 << w;
+  L.full = ncls - 1;
+  L.njoin = ncls >> 1;
+  for (int c = 0; c < kMaxClasses; ++c) L.views[c] = make_view(pin, c < ncls ? c : 0);
+  L.tiles_before[0] = 0;
+  for (int j = 0; j < kMaxClasses / 2; ++j) {
+    uint64_t len = 0;
+    if (j < L.njoin) len = L.views[j].size() + L.views[j ^ L.full].size();
+    L.tiles_before[j + 1] = L.tiles_before[j] + (len + tile - 1) / tile;
+  }
+}
+
 // ---------------------------------------------------------------------------
-// The gate kernel.
+// Merge-path partition: one wavefront per tile boundary, 64-ary search of the
+// co-rank (number of class-A strings among the first d of the merged
+// sequence, A first on equal keys), then a pair split by the boundary is
+// moved into the earlier tile.
+template <int NW>
+__global__ __launch_bounds__(256) void partition_kernel(GateParams gp, Side in, const Plan* __restrict__ plan_in,
+                                                         uint64_t* __restrict__ part, Ctl* __restrict__ ctl) {
+  __shared__ JoinLayout L;
+  if (threadIdx.x == 0) make_layout(L, plan_in, gp.w, gp.tile);
+  __syncthreads();
+  if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kErrNone) return;
+  const int lane = threadIdx.x & 63;
+  const uint64_t b = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  // boundary b -> join j, local boundary tl (join j owns tiles_before[j]+j .. tiles_before[j+1]+j)
+  int j = -1;
+  uint64_t tl = 0;
+  for (int q = 0; q < L.njoin; ++q) {
+    const uint64_t first = L.tiles_before[q] + q, last = L.tiles_before[q + 1] + q;
+    if (b >= first && b <= last) {
+      j = q;
+      tl = b - first;
+    }
+  }
+  if (j < 0) return;
+  if (b >= gp.status_cap + kMaxClasses) {
+    if (lane == 0) atomicMax(&ctl->error, kErrCapacity);
+    return;
+  }
+  const ClassView& VA = L.views[j];
+  const ClassView& VB = L.views[j ^ L.full];
+  const uint64_t nA = VA.size(), nB = VB.size(), len = nA + nB;
+  const uint64_t d = (tl * (uint64_t)gp.tile < len) ? tl * (uint64_t)gp.tile : len;
+  const int nbits = gp.nbits, w = gp.w;
+  uint64_t lo = d > nB ? d - nB : 0;
+  uint64_t hi = d < nA ? d : nA;  // answer in [lo, hi]
+  while (hi > lo) {
+    const uint64_t range = hi - lo;
+    const uint64_t step = (range + 63) / 64;
+    const uint64_t i = lo + (uint64_t)lane * step;
+    bool pred = false;
+    if (i < hi) {
+      Key<NW> a = load_key<NW>(in, VA.phys(i));
+      Key<NW> bb = xor_top(load_key<NW>(in, VB.phys(d - i - 1)), nbits, w);
+      pred = !key_less(bb, a);  // A[i] <= B'[d-i-1]: the answer is above i
+    }
+    const uint64_t mask = __ballot(pred);
+    const int cnt = __popcll(mask);
+    if (step == 1) {
+      lo = lo + (uint64_t)cnt;
+      break;
+    }
+    const uint64_t nlo = cnt == 0 ? lo : lo + (uint64_t)(cnt - 1) * step + 1;
+    const uint64_t nhi_c = lo + (uint64_t)cnt * step;
+    hi = nhi_c < hi ? nhi_c : hi;
+    lo = nlo;
+  }
+  if (lane == 0) {
+    uint64_t i = lo, jj = d - lo;
+    if (i > 0 && jj < nB) {
+      Key<NW> a = load_key<NW>(in, VA.phys(i - 1));
+      Key<NW> bb = xor_top(load_key<NW>(in, VB.phys(jj)), nbits, w);
+      if (key_eq(a, bb)) jj += 1;
+    }
+    part[2 * b] = i;
+    part[2 * b + 1] = jj;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The gate kernel: one merge-path tile per ticket (persistent workgroups).
+//
+// Per tile: (1) load the A range (class cA) and the B range (class cB, keys
+// xored with the gate into cA's key space) with the previous gate's filter
+// and normalisation applied; (2) every thread walks a contiguous run of the
+// merged order (A before B on equal keys; an equal pair is one partner pair
+// of Eq. ITPP_PropRules), computes the outputs and numbers them inside its
+// run per output stream and next class; (3) a block scan turns run counts
+// into tile ranks, a look-back across tiles of the same join turns them into
+// region positions; (4) every element writes its outputs.
 template <int NW, int BLOCK, int TILE>
 struct GateSmem {
   static constexpr int CAPT = TILE + 2;
+  static constexpr int PER = (CAPT + BLOCK - 1) / BLOCK;
   uint64_t key[NW][CAPT];
   double coef[CAPT];
-  uint8_t flag[CAPT];      // bit0 survive, bit1 commuting
-  uint64_t vs[CAPT + 1];   // self one-hot (16-bit lanes per next class), then exclusive scan
-  uint64_t vb[CAPT + 1];   // branch one-hot, then exclusive scan
+  uint16_t info[CAPT];  // bit0 survive, bit1 commuting, bit2 paired, bit3 self, bits4-5 its class,
+                        // bit6 branch, bits7-8 its class
+  uint16_t partner[CAPT];
+  uint16_t rs[CAPT], rb[CAPT];  // ranks of the self / branch output inside the tile's stream and class
+  uint64_t tot0, tot1;          // tile totals per next class (16-bit lanes): stream cA, stream cB
   uint64_t wa[BLOCK / 64], wb[BLOCK / 64];
   uint32_t hist[kHistBins];
+  uint32_t fhist[kFineBins];
   uint32_t ncnt[kMaxClasses * kMaxClasses];
   uint64_t out_base[kMaxClasses + 1][kMaxClasses];  // row kMaxClasses holds the total
   uint32_t excl[2 * kMaxClasses];
-  uint64_t i0, j0, i1, j1;
   uint32_t tile;
-  uint32_t nwritten;
-  ClassView views[kMaxClasses];
-  uint64_t tiles_before[kMaxClasses / 2 + 1];
+  uint32_t nwritten, nabove;
+  JoinLayout L;
 };
 
-template <int NW>
-__device__ inline uint64_t corank(const Side& in, const ClassView& A, const ClassView& B, uint64_t d,
-                                  int nbits, int w) {
-  const uint64_t nA = A.size(), nB = B.size();
-  uint64_t lo = d > nB ? d - nB : 0;
-  uint64_t hi = d < nA ? d : nA;
-  while (lo < hi) {
-    const uint64_t mid = (lo + hi) >> 1;
-    Key<NW> a = load_key<NW>(in, A.phys(mid));
-    Key<NW> b = xor_top(load_key<NW>(in, B.phys(d - mid - 1)), nbits, w);
-    if (!key_less(b, a))  // a <= b'
-      lo = mid + 1;
-    else
-      hi = mid;
+__device__ __forceinline__ uint64_t phys_sel(const ClassView& v, uint64_t i) {
+  uint64_t b = v.base[0], st = 0;
+#pragma unroll
+  for (int t = 1; t < kMaxClasses; ++t) {
+    const bool in = (t < v.nseg) && (i >= v.start[t]);
+    b = in ? v.base[t] : b;
+    st = in ? v.start[t] : st;
   }
-  return lo;
+  return b + (i - st);
+}
+
+template <int NW, int TILE>
+__device__ __forceinline__ Key<NW> lds_key(const uint64_t (*key)[TILE + 2], int x) {
+  Key<NW> k;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) k.w[q] = key[q][x];
+  return k;
+}
+
+// New value of an element (Eq. ITPP_PropRules, then the branch of an
+// unpaired commuting string).
+template <int NW>
+__device__ __forceinline__ void element_values(const Key<NW>& own, double c, bool comm, bool paired, double cp,
+                                               const GateParams& gp, Ctl* ctl, double& vs, double& vb) {
+  vb = 0.0;
+  if (!comm) {
+    vs = c;
+    return;
+  }
+  const int e4 = phase_negative(own, gp);
+  if (e4 & 1) atomicMax(&ctl->error, kErrPhase);
+  const bool neg = (e4 == 2);  // Q P = -R
+  const double t1 = __dmul_rn(gp.ch, c);
+  if (paired) {
+    double t2 = __dmul_rn(gp.sh, cp);
+    if (!neg) t2 = -t2;
+    vs = __dadd_rn(t1, t2);
+  } else {
+    vs = t1;
+    double t2 = __dmul_rn(gp.sh, c);
+    if (!neg) t2 = -t2;
+    vb = t2;
+  }
 }
 
 template <int NW, int BLOCK, int TILE>
-__global__ __launch_bounds__(BLOCK) void gate_kernel(GateParams gp, Side in, Side out,
+__global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, Side out,
                                                       const Plan* __restrict__ plan_in,
                                                       Plan* __restrict__ plan_out,
                                                       const Filter* __restrict__ filt_in,
+                                                      const uint64_t* __restrict__ part,
                                                       Ctl* __restrict__ ctl,
                                                       TileStatus* __restrict__ status) {
   using Smem = GateSmem<NW, BLOCK, TILE>;
+  constexpr int PER = Smem::PER;
   __shared__ Smem sm;
-  constexpr int ITEMS = (TILE + 2 + BLOCK - 1) / BLOCK;
   const int tid = threadIdx.x;
-  const Plan pin = *plan_in;
+  const int lane = tid & 63;
   const Filter fin = *filt_in;
   const int nbits = gp.nbits;
   const int w = gp.w;
   const int ncls = 1 << w;
   const int full = ncls - 1;
   const int ncls1 = 1 << gp.w1;
-  const int njoin = ncls >> 1;
+  // fine histogram window around the value predicted from the previous cap
+  uint64_t win_lo = 0, win_hi = 0;
+  if (fin.cap_active) {
+    const double pred = __longlong_as_double((long long)fin.kth_bits) / fin.cI;
+    const uint64_t cb = abs_bits(pred);
+    win_lo = cb > kFineHalf ? cb - kFineHalf : 0;
+    win_hi = win_lo + 2 * kFineHalf;
+  }
 
   for (int i = tid; i < kHistBins; i += BLOCK) sm.hist[i] = 0;
+  for (int i = tid; i < kFineBins; i += BLOCK) sm.fhist[i] = 0;
   if (tid < kMaxClasses * kMaxClasses) sm.ncnt[tid] = 0;
   if (tid == 0) {
+    const Plan* __restrict__ pin = plan_in;
     // output region capacities: cap(c,e) = n[c][e] + n[~c][e ^ ov]
     uint64_t acc = 0;
     for (int c = 0; c < kMaxClasses; ++c)
       for (int e = 0; e < kMaxClasses; ++e) {
         sm.out_base[c][e] = acc;
-        if (c < ncls && e < ncls1) acc += (uint64_t)pin.ncnt[c][e] + (uint64_t)pin.ncnt[c ^ full][e ^ gp.ov];
+        if (c < ncls && e < ncls1) acc += (uint64_t)pin->ncnt[c][e] + (uint64_t)pin->ncnt[c ^ full][e ^ gp.ov];
       }
     for (int e = 0; e < kMaxClasses; ++e) sm.out_base[kMaxClasses][e] = acc;
     if (acc > gp.cap_elems) atomicMax(&ctl->error, kErrCapacity);
@@ -372,21 +527,13 @@ __global__ __launch_bounds__(BLOCK) void gate_kernel(GateParams gp, Side in, Sid
       plan_out->we = gp.w1;
     }
     sm.nwritten = 0;
-  }
-  if (tid == 0) {
-    for (int c = 0; c < kMaxClasses; ++c) sm.views[c] = make_view(pin, c < ncls ? c : 0);
-    sm.tiles_before[0] = 0;
-    for (int j = 0; j < kMaxClasses / 2; ++j) {
-      uint64_t L = 0;
-      if (j < njoin) L = sm.views[j].size() + sm.views[j ^ full].size();
-      sm.tiles_before[j + 1] = sm.tiles_before[j] + (L + TILE - 1) / TILE;
-    }
+    sm.nabove = 0;
+    make_layout(sm.L, pin, w, TILE);
   }
   __syncthreads();
-  const uint64_t total_tiles = sm.tiles_before[njoin];
+  const uint64_t total_tiles = sm.L.tiles_before[sm.L.njoin];
   if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kErrNone) return;
 
-  uint64_t my_written = 0;
   for (;;) {
     if (tid == 0) sm.tile = atomicAdd(&ctl->ticket, 1u);
     __syncthreads();
@@ -397,43 +544,25 @@ __global__ __launch_bounds__(BLOCK) void gate_kernel(GateParams gp, Side in, Sid
       break;
     }
     int j = 0;
-    while (j + 1 < njoin && t >= sm.tiles_before[j + 1]) ++j;
-    const uint64_t tl = t - sm.tiles_before[j];
+    while (j + 1 < sm.L.njoin && t >= sm.L.tiles_before[j + 1]) ++j;
+    const uint64_t tl = t - sm.L.tiles_before[j];
     const int cA = j, cB = j ^ full;
-    const ClassView& VA = sm.views[cA];
-    const ClassView& VB = sm.views[cB];
-    const uint64_t nA = VA.size(), nB = VB.size();
-    const uint64_t L = nA + nB;
-    const uint64_t d0 = tl * TILE;
-    const uint64_t d1 = (d0 + TILE < L) ? d0 + TILE : L;
-    // merge-path co-ranks, pairs kept in the earlier tile
-    if (tid == 0 || tid == 64) {
-      const uint64_t d = (tid == 0) ? d0 : d1;
-      uint64_t i = corank<NW>(in, VA, VB, d, nbits, w);
-      uint64_t jj = d - i;
-      if (i > 0 && jj < nB) {
-        Key<NW> a = load_key<NW>(in, VA.phys(i - 1));
-        Key<NW> b = xor_top(load_key<NW>(in, VB.phys(jj)), nbits, w);
-        if (key_eq(a, b)) jj += 1;
-      }
-      if (tid == 0) {
-        sm.i0 = i;
-        sm.j0 = jj;
-      } else {
-        sm.i1 = i;
-        sm.j1 = jj;
-      }
-    }
-    __syncthreads();
-    const uint64_t i0 = sm.i0, j0 = sm.j0;
-    const int nAt = (int)(sm.i1 - sm.i0);
-    const int nBt = (int)(sm.j1 - sm.j0);
+    const ClassView VA = sm.L.views[cA];
+    const ClassView VB = sm.L.views[cB];
+    const uint64_t pb = sm.L.tiles_before[j] + (uint64_t)j + tl;
+    const uint64_t i0 = part[2 * pb], j0 = part[2 * pb + 1];
+    const int nAt = (int)(part[2 * pb + 2] - i0);
+    const int nBt = (int)(part[2 * pb + 3] - j0);
     const int nt = nAt + nBt;
+    if (nt > TILE + 1 || nAt < 0 || nBt < 0) {
+      if (tid == 0) atomicMax(&ctl->error, kErrCapacity);
+      break;
+    }
 
-    // load, filter, normalise
+    // (1) load, filter, normalise
     for (int x = tid; x < nt; x += BLOCK) {
       const bool isA = x < nAt;
-      const uint64_t p = isA ? VA.phys(i0 + x) : VB.phys(j0 + (x - nAt));
+      const uint64_t p = isA ? phys_sel(VA, i0 + x) : phys_sel(VB, j0 + (x - nAt));
       Key<NW> k = load_key<NW>(in, p);
       const double cs = in.coef[p];
       const bool sv = survives(k, cs, fin, gp.pos_in, nbits);
@@ -442,271 +571,295 @@ __global__ __launch_bounds__(BLOCK) void gate_kernel(GateParams gp, Side in, Sid
 #pragma unroll
       for (int q = 0; q < NW; ++q) sm.key[q][x] = k.w[q];
       sm.coef[x] = cs / fin.cI;
-      sm.flag[x] = (uint8_t)((sv ? 1 : 0) | (comm ? 2 : 0));
+      sm.info[x] = (uint16_t)((sv ? 1 : 0) | (comm ? 2 : 0));
     }
     __syncthreads();
 
-    // partner search, outputs, one-hot class vectors
-    double vself[ITEMS], vbr[ITEMS];
-    uint32_t lbo[ITEMS];
-    uint8_t eo[ITEMS];  // low nibble: self class, high nibble: branch class
+    // (2) merge walk over merged positions [m0, m0 + PER)
+    uint64_t c0 = 0, c1 = 0;  // run counts per next class (16-bit lanes): stream cA, stream cB
+    int xs[2 * (PER + 1)];    // elements handled by this thread, slot 2*step+side
 #pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-      const int x = tid + it * BLOCK;
-      vself[it] = 0.0;
-      vbr[it] = 0.0;
-      lbo[it] = 0;
-      eo[it] = 0;
-      uint64_t onehot_s = 0, onehot_b = 0;
-      if (x < nt) {
-        const bool isA = x < nAt;
-        Key<NW> k;
-#pragma unroll
-        for (int q = 0; q < NW; ++q) k.w[q] = sm.key[q][x];
-        // lower bound of k in the other range
-        int lo = isA ? nAt : 0;
-        int hi = isA ? nt : nAt;
-        const int base = lo;
+    for (int q = 0; q < 2 * (PER + 1); ++q) xs[q] = -1;
+    {
+      const int m0 = tid * PER;
+      const int m1 = (m0 + PER < nt) ? m0 + PER : nt;
+      if (m0 < nt) {
+        int lo = m0 > nBt ? m0 - nBt : 0;
+        int hi = m0 < nAt ? m0 : nAt;
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
-          Key<NW> m;
-#pragma unroll
-          for (int q = 0; q < NW; ++q) m.w[q] = sm.key[q][mid];
-          if (key_less(m, k))
+          const Key<NW> a = lds_key<NW, TILE>(sm.key, mid);
+          const Key<NW> b = lds_key<NW, TILE>(sm.key, nAt + (m0 - mid - 1));
+          if (!key_less(b, a))
             lo = mid + 1;
           else
             hi = mid;
         }
-        const int lb = lo - base;
-        lbo[it] = (uint32_t)lb;
-        const uint8_t fl = sm.flag[x];
-        if (fl & 1) {
-          bool paired = false;
-          double cp = 0.0;
-          if (lo < (isA ? nt : nAt)) {
-            Key<NW> m;
-#pragma unroll
-            for (int q = 0; q < NW; ++q) m.w[q] = sm.key[q][lo];
-            if (key_eq(m, k) && (sm.flag[lo] & 1)) {
-              paired = true;
-              cp = sm.coef[lo];
-            }
-          }
-          const double c = sm.coef[x];
-          // own key in this gate's rep
-          const Key<NW> own = isA ? k : xor_top(k, nbits, w);
-          const Key<NW> brk = isA ? xor_top(k, nbits, w) : k;
-          bool hs = false, hb = false;
-          if (!(fl & 2)) {
-            vself[it] = c;
-            hs = fabs(c) > gp.delta;
-          } else {
-            const int e4 = phase_negative(own, gp);
-            if (e4 & 1) atomicMax(&ctl->error, kErrPhase);
-            const bool neg = (e4 == 2);  // Q P = -R
-            const double t1 = __dmul_rn(gp.ch, c);
-            if (paired) {
-              double t2 = __dmul_rn(gp.sh, cp);
-              if (!neg) t2 = -t2;
-              vself[it] = __dadd_rn(t1, t2);
-            } else {
-              vself[it] = t1;
-              double t2 = __dmul_rn(gp.sh, c);
-              if (!neg) t2 = -t2;
-              vbr[it] = t2;
-              hb = fabs(t2) > gp.delta;
-            }
-            hs = fabs(vself[it]) > gp.delta;
-          }
-          Key<NW> ks = own, kb = brk;
-          for (int m = 0; m < gp.w1; ++m) {
-            ks = move_top(ks, gp.mv[m], nbits);
-            kb = move_top(kb, gp.mv[m], nbits);
-          }
-          const int es = class_of(ks, nbits, gp.w1);
-          const int eb = class_of(kb, nbits, gp.w1);
-          eo[it] = (uint8_t)(es | (eb << 4));
-          if (hs) onehot_s = 1ull << (16 * es);
-          if (hb) onehot_b = 1ull << (16 * eb);
-          if (!hs) vself[it] = 0.0, eo[it] |= 0x08;  // mark no self
-          if (!hb) eo[it] |= 0x80;                   // mark no branch
-        } else {
-          eo[it] = 0x88;
+        int a = lo, b = m0 - lo;
+        if (a > 0 && b < nBt) {
+          if (key_eq(lds_key<NW, TILE>(sm.key, a - 1), lds_key<NW, TILE>(sm.key, nAt + b))) ++b;
         }
-      }
-      if (x < TILE + 2) {
-        sm.vs[x] = onehot_s;
-        sm.vb[x] = onehot_b;
+#pragma unroll
+        for (int step = 0; step <= PER; ++step) {
+          if (a + b >= m1) break;
+          const bool haveA = a < nAt, haveB = b < nBt;
+          Key<NW> ka, kb;
+          if (haveA) ka = lds_key<NW, TILE>(sm.key, a);
+          if (haveB) kb = lds_key<NW, TILE>(sm.key, nAt + b);
+          const bool takeA = haveA && (!haveB || !key_less(kb, ka));
+          const bool eq = takeA && haveB && key_eq(ka, kb);
+          // elements handled in this step: A[a] (if takeA), B[b] (if !takeA or eq)
+#pragma unroll
+          for (int side = 0; side < 2; ++side) {
+            const bool isA = side == 0;
+            if (isA && !takeA) continue;
+            if (!isA && takeA && !eq) continue;
+            const int x = isA ? a : nAt + b;
+            const int y = isA ? nAt + b : a;  // partner slot if eq
+            uint16_t inf = sm.info[x];
+            const bool sv = inf & 1, comm = (inf >> 1) & 1;
+            uint16_t rsx = 0, rbx = 0;
+            if (sv) {
+              const bool paired = eq && (sm.info[y] & 1);
+              const double c = sm.coef[x];
+              const double cp = paired ? sm.coef[y] : 0.0;
+              const Key<NW> k = isA ? ka : kb;
+              const Key<NW> ownk = isA ? k : xor_top(k, nbits, w);
+              const Key<NW> brk = isA ? xor_top(k, nbits, w) : k;
+              double vs, vb;
+              element_values(ownk, c, comm, paired, cp, gp, ctl, vs, vb);
+              const bool hs = fabs(vs) > gp.delta;
+              const bool hb = comm && !paired && fabs(vb) > gp.delta;
+              if (paired) {
+                inf |= 4u;
+                sm.partner[x] = (uint16_t)y;
+              }
+              if (hs) {
+                Key<NW> ks = ownk;
+                for (int mm = 0; mm < gp.w1; ++mm) ks = move_top(ks, gp.mv[mm], nbits);
+                const int es = class_of(ks, nbits, gp.w1);
+                inf |= (uint16_t)(8u | (es << 4));
+                uint64_t& cc = isA ? c0 : c1;
+                rsx = (uint16_t)lane16(cc, es);
+                cc += 1ull << (16 * es);
+              }
+              if (hb) {
+                Key<NW> kk = brk;
+                for (int mm = 0; mm < gp.w1; ++mm) kk = move_top(kk, gp.mv[mm], nbits);
+                const int eb = class_of(kk, nbits, gp.w1);
+                inf |= (uint16_t)(64u | (eb << 7));
+                uint64_t& cc = isA ? c1 : c0;
+                rbx = (uint16_t)lane16(cc, eb);
+                cc += 1ull << (16 * eb);
+              }
+            }
+            sm.info[x] = inf;
+            sm.rs[x] = rsx;
+            sm.rb[x] = rbx;
+            xs[2 * step + side] = x;
+          }
+          if (takeA) ++a;
+          if (!takeA || eq) ++b;
+        }
       }
     }
-    __syncthreads();
-    // exclusive scans over [0, nt) in blocked layout; entry nt = total
+    // (3) block scan of the run counts; ranks of this thread's outputs become tile ranks
     {
-      constexpr int PER = ITEMS;
-      const int s0 = tid * PER;
-      uint64_t la[PER], lb2[PER];
-      uint64_t suma = 0, sumb = 0;
+      uint64_t t0, t1;
+      uint64_t p0 = c0, p1 = c1;
+      block_scan2<BLOCK>(p0, p1, sm.wa, sm.wb, t0, t1);
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int x = s0 + q;
-        la[q] = (x < nt) ? sm.vs[x] : 0;
-        lb2[q] = (x < nt) ? sm.vb[x] : 0;
-        suma += la[q];
-        sumb += lb2[q];
-      }
-      uint64_t pa = suma, pb = sumb, ta, tb;
-      block_scan2<BLOCK>(pa, pb, sm.wa, sm.wb, ta, tb);
-#pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int x = s0 + q;
-        if (x < nt) {
-          sm.vs[x] = pa;
-          sm.vb[x] = pb;
-        }
-        pa += la[q];
-        pb += lb2[q];
+      for (int q = 0; q < 2 * (PER + 1); ++q) {
+        const int x = xs[q];
+        if (x < 0) continue;
+        const uint16_t inf = sm.info[x];
+        const bool isA = x < nAt;
+        if (inf & 8u) sm.rs[x] = (uint16_t)(sm.rs[x] + lane16(isA ? p0 : p1, (inf >> 4) & 3));
+        if (inf & 64u) sm.rb[x] = (uint16_t)(sm.rb[x] + lane16(isA ? p1 : p0, (inf >> 7) & 3));
       }
       if (tid == 0) {
-        sm.vs[nt] = ta;
-        sm.vb[nt] = tb;
+        sm.tot0 = t0;
+        sm.tot1 = t1;
       }
     }
     __syncthreads();
-    // tile totals per (side, next class) and look-back
-    if (tid == 0) {
-      const uint64_t As = sm.vs[nAt], Ab = sm.vb[nAt];
-      const uint64_t Bs = sm.vs[nt] - As, Bb = sm.vb[nt] - Ab;
+    // look-back across the tiles of this join (wave 0)
+    if (tid < 64) {
       uint32_t agg[2 * kMaxClasses];
+#pragma unroll
       for (int e = 0; e < kMaxClasses; ++e) {
-        agg[e] = lane16(As, e) + lane16(Bb, e);                // class cA stream
-        agg[kMaxClasses + e] = lane16(Bs, e) + lane16(Ab, e);  // class cB stream
+        agg[e] = lane16(sm.tot0, e);
+        agg[kMaxClasses + e] = lane16(sm.tot1, e);
       }
+      constexpr int NQ = 2 * kMaxClasses;
       TileStatus* st = status + t;
-      const uint32_t ep = gp.epoch << 2;
-      uint32_t excl[2 * kMaxClasses];
-      for (int q = 0; q < 2 * kMaxClasses; ++q) excl[q] = 0;
+      const unsigned long long tag = (unsigned long long)gp.epoch << 32;
+      uint32_t excl[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) excl[q] = 0;
       if (tl == 0) {
-        for (int q = 0; q < 2 * kMaxClasses; ++q)
-          __hip_atomic_store(&st->incl[q], agg[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&st->flag, ep | 2u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        for (int q = 0; q < 2 * kMaxClasses; ++q)
-          __hip_atomic_store(&st->agg[q], agg[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&st->flag, ep | 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        int64_t k = (int64_t)t - 1;
-        const int64_t first = (int64_t)sm.tiles_before[j];
-        while (k >= first) {
-          TileStatus* ps = status + k;
-          uint32_t f = 0;
-          uint32_t spins = 0;
-          for (;;) {
-            f = __hip_atomic_load(&ps->flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-            if ((f >> 2) == gp.epoch && (f & 3u) != 0) break;
-            if (++spins > (1u << 26)) {
-              atomicMax(&ctl->error, kErrSpin);
-              f = ep | 2u;
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-          }
-          if ((f & 3u) == 2u) {
-            for (int q = 0; q < 2 * kMaxClasses; ++q)
-              excl[q] += __hip_atomic_load(&ps->incl[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
-          }
-          for (int q = 0; q < 2 * kMaxClasses; ++q)
-            excl[q] += __hip_atomic_load(&ps->agg[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          --k;
+        if (lane == 0) {
+#pragma unroll
+          for (int q = 0; q < NQ; ++q)
+            __hip_atomic_store(&st->w[NQ + q], tag | agg[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        for (int q = 0; q < 2 * kMaxClasses; ++q)
-          __hip_atomic_store(&st->incl[q], excl[q] + agg[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&st->flag, ep | 2u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        if (lane == 0) {
+#pragma unroll
+          for (int q = 0; q < NQ; ++q)
+            __hip_atomic_store(&st->w[q], tag | agg[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // each lane inspects LB consecutive predecessors per round (window 64 * LB)
+        constexpr int LB = 2;
+        const int64_t first = (int64_t)sm.L.tiles_before[j];
+        int64_t khi = (int64_t)t - 1;
+        bool done = false;
+        while (!done) {
+          uint32_t val[LB][NQ];
+          int kind[LB];  // 0 aggregate, 1 inclusive (or before the join: zero)
+#pragma unroll
+          for (int r = 0; r < LB; ++r) {
+            const int64_t k = khi - (int64_t)(lane * LB + r);
+            kind[r] = 1;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) val[r][q] = 0;
+            if (k < first) continue;
+            uint32_t spins = 0;
+            for (;;) {
+              unsigned long long wv[2 * NQ];
+#pragma unroll
+              for (int q = 0; q < 2 * NQ; ++q)
+                wv[q] = __hip_atomic_load(&status[k].w[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              bool av = true, iv = true;
+#pragma unroll
+              for (int q = 0; q < NQ; ++q) {
+                av = av && ((wv[q] >> 32) == gp.epoch);
+                iv = iv && ((wv[NQ + q] >> 32) == gp.epoch);
+              }
+              if (iv || av) {
+                kind[r] = iv ? 1 : 0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) val[r][q] = (uint32_t)(iv ? wv[NQ + q] : wv[q]);
+                break;
+              }
+              if (++spins > (1u << 22)) {
+                atomicMax(&ctl->error, kErrSpin);
+                break;
+              }
+              __builtin_amdgcn_s_sleep(1);
+            }
+          }
+          // nearest inclusive predecessor: lowest (lane, r) position with kind 1
+          int pos_incl = 64 * LB;
+#pragma unroll
+          for (int r = LB - 1; r >= 0; --r)
+            if (kind[r]) pos_incl = lane * LB + r;
+          uint32_t best = (uint32_t)pos_incl;
+#pragma unroll
+          for (int d = 32; d >= 1; d >>= 1) {
+            const uint32_t o = __shfl_xor(best, d, 64);
+            best = o < best ? o : best;
+          }
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int r = 0; r < LB; ++r)
+              if ((uint32_t)(lane * LB + r) <= best) v += val[r][q];
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+            excl[q] += v;
+          }
+          done = best < (uint32_t)(64 * LB);
+          khi -= 64 * LB;
+        }
+        if (lane == 0) {
+#pragma unroll
+          for (int q = 0; q < NQ; ++q)
+            __hip_atomic_store(&st->w[NQ + q], tag | (excl[q] + agg[q]), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
       }
-      for (int q = 0; q < 2 * kMaxClasses; ++q) sm.excl[q] = excl[q];
-      // the last tile of the join publishes the region fill counts
-      if (t + 1 == sm.tiles_before[j + 1]) {
-        for (int e = 0; e < ncls1; ++e) {
-          plan_out->cnt[cA][e] = excl[e] + agg[e];
-          plan_out->cnt[cB][e] = excl[kMaxClasses + e] + agg[kMaxClasses + e];
+      if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 2 * kMaxClasses; ++q) sm.excl[q] = excl[q];
+        // the last tile of the join publishes the region fill counts
+        if (t + 1 == sm.L.tiles_before[j + 1]) {
+#pragma unroll
+          for (int e = 0; e < kMaxClasses; ++e) {
+            if (e < ncls1) {
+              plan_out->cnt[cA][e] = excl[e] + agg[e];
+              plan_out->cnt[cB][e] = excl[kMaxClasses + e] + agg[kMaxClasses + e];
+            }
+          }
         }
       }
     }
     __syncthreads();
-    // write outputs
-#pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-      const int x = tid + it * BLOCK;
-      if (x >= nt) continue;
-      const uint8_t e = eo[it];
-      const bool hs = !(e & 0x08);
-      const bool hb = !(e & 0x80);
-      if (!hs && !hb) continue;
+    // (4) write outputs
+    uint32_t written = 0, above = 0;
+    for (int x = tid; x < nt; x += BLOCK) {
+      const uint16_t inf = sm.info[x];
+      if (!(inf & (8u | 64u))) continue;
       const bool isA = x < nAt;
-      const int lb = (int)lbo[it];
-      Key<NW> k;
-#pragma unroll
-      for (int q = 0; q < NW; ++q) k.w[q] = sm.key[q][x];
-      const Key<NW> own = isA ? k : xor_top(k, nbits, w);
-      const Key<NW> brk = isA ? xor_top(k, nbits, w) : k;
-      // prefix values at this element and at the partner rank in the other range
-      const uint64_t my_s = sm.vs[x], my_b = sm.vb[x];
-      uint64_t oth_s, oth_b;
-      if (isA) {
-        oth_s = sm.vs[nAt + lb] - sm.vs[nAt];
-        oth_b = sm.vb[nAt + lb] - sm.vb[nAt];
-      } else {
-        oth_s = sm.vs[lb];
-        oth_b = sm.vb[lb];
-      }
-      const uint64_t mys = isA ? my_s : my_s - sm.vs[nAt];
-      const uint64_t myb = isA ? my_b : my_b - sm.vb[nAt];
-      if (hs) {
-        const int es = e & 0x7;
-        // self output: stream of own class
-        const int side = isA ? 0 : 1;
+      const Key<NW> k = lds_key<NW, TILE>(sm.key, x);
+      const Key<NW> ownk = isA ? k : xor_top(k, nbits, w);
+      const bool paired = (inf >> 2) & 1;
+      double vs, vb;
+      element_values(ownk, sm.coef[x], (inf >> 1) & 1, paired, paired ? sm.coef[sm.partner[x]] : 0.0, gp, ctl,
+                     vs, vb);
+      if (inf & 8u) {
+        const int es = (inf >> 4) & 3;
+        const int stream = isA ? 0 : 1;
         const int cls = isA ? cA : cB;
-        const uint64_t pos = sm.out_base[cls][es] + sm.excl[side * kMaxClasses + es] + lane16(mys, es) +
-                             lane16(oth_b, es);
-        Key<NW> ks = own;
-        for (int m = 0; m < gp.w1; ++m) ks = move_top(ks, gp.mv[m], nbits);
-        if (pos >= region_end(sm.out_base, cls, es, ncls, ncls1)) {
+        const uint64_t pos = sm.out_base[cls][es] + sm.excl[stream * kMaxClasses + es] + sm.rs[x];
+        Key<NW> ks = ownk;
+        for (int mm = 0; mm < gp.w1; ++mm) ks = move_top(ks, gp.mv[mm], nbits);
+        if (pos >= region_end(sm.out_base, cls, es)) {
           atomicMax(&ctl->error, kErrCapacity);
-          continue;
-        }
-        store_key<NW>(out, pos, ks);
-        out.coef[pos] = vself[it];
-        if (key_zero(ks)) {
-          ctl->cI_out = vself[it];
-          ctl->have_cI = 1u;
         } else {
-          atomicAdd(&sm.hist[hist_bin(abs_bits(vself[it]))], 1u);
-          ++my_written;
+          store_key<NW>(out, pos, ks);
+          out.coef[pos] = vs;
+          if (key_zero(ks)) {
+            ctl->cI_out = vs;
+            ctl->have_cI = 1u;
+          } else {
+            const uint64_t bits = abs_bits(vs);
+            atomicAdd(&sm.hist[hist_bin(bits)], 1u);
+            if (bits >= win_hi) ++above;
+            else if (bits >= win_lo) atomicAdd(&sm.fhist[(bits - win_lo) >> kFineShift], 1u);
+            ++written;
+          }
+          int f = 0;
+          for (int bq = 0; bq < gp.w2; ++bq) f |= get_bit(ks, gp.fpos[bq]) << bq;
+          atomicAdd(&sm.ncnt[es * kMaxClasses + f], 1u);
         }
-        int f = 0;
-        for (int b = 0; b < gp.w2; ++b) f |= get_bit(ks, gp.fpos[b]) << b;
-        atomicAdd(&sm.ncnt[es * kMaxClasses + f], 1u);
       }
-      if (hb) {
-        const int eb = (e >> 4) & 0x7;
-        const int side = isA ? 1 : 0;
+      if (inf & 64u) {
+        const int eb = (inf >> 7) & 3;
+        const int stream = isA ? 1 : 0;
         const int cls = isA ? cB : cA;
-        const uint64_t pos = sm.out_base[cls][eb] + sm.excl[side * kMaxClasses + eb] + lane16(myb, eb) +
-                             lane16(oth_s, eb);
-        Key<NW> kb = brk;
-        for (int m = 0; m < gp.w1; ++m) kb = move_top(kb, gp.mv[m], nbits);
-        if (pos >= region_end(sm.out_base, cls, eb, ncls, ncls1)) {
+        const uint64_t pos = sm.out_base[cls][eb] + sm.excl[stream * kMaxClasses + eb] + sm.rb[x];
+        Key<NW> kb = isA ? xor_top(k, nbits, w) : k;
+        for (int mm = 0; mm < gp.w1; ++mm) kb = move_top(kb, gp.mv[mm], nbits);
+        if (pos >= region_end(sm.out_base, cls, eb)) {
           atomicMax(&ctl->error, kErrCapacity);
-          continue;
+        } else {
+          store_key<NW>(out, pos, kb);
+          out.coef[pos] = vb;
+          const uint64_t bits = abs_bits(vb);
+          atomicAdd(&sm.hist[hist_bin(bits)], 1u);
+          if (bits >= win_hi) ++above;
+          else if (bits >= win_lo) atomicAdd(&sm.fhist[(bits - win_lo) >> kFineShift], 1u);
+          ++written;
+          int f = 0;
+          for (int bq = 0; bq < gp.w2; ++bq) f |= get_bit(kb, gp.fpos[bq]) << bq;
+          atomicAdd(&sm.ncnt[eb * kMaxClasses + f], 1u);
         }
-        store_key<NW>(out, pos, kb);
-        out.coef[pos] = vbr[it];
-        atomicAdd(&sm.hist[hist_bin(abs_bits(vbr[it]))], 1u);
-        ++my_written;
-        int f = 0;
-        for (int b = 0; b < gp.w2; ++b) f |= get_bit(kb, gp.fpos[b]) << b;
-        atomicAdd(&sm.ncnt[eb * kMaxClasses + f], 1u);
       }
     }
+    if (written) atomicAdd(&sm.nwritten, written);
+    if (above) atomicAdd(&sm.nabove, above);
     __syncthreads();
   }
   // flush per-workgroup statistics
@@ -715,16 +868,20 @@ __global__ __launch_bounds__(BLOCK) void gate_kernel(GateParams gp, Side in, Sid
     const uint32_t v = sm.hist[i];
     if (v) atomicAdd(&ctl->hist[i], v);
   }
+  if (win_hi > win_lo)
+    for (int i = tid; i < kFineBins; i += BLOCK) {
+      const uint32_t v = sm.fhist[i];
+      if (v) atomicAdd(&ctl->fhist[i], v);
+    }
   if (tid < kMaxClasses * kMaxClasses) {
     const uint32_t v = sm.ncnt[tid];
     if (v) atomicAdd(&plan_out->ncnt[tid / kMaxClasses][tid % kMaxClasses], v);
   }
-  if (my_written) atomicAdd(&sm.nwritten, (uint32_t)my_written);
-  __syncthreads();
-  if (tid == 0 && sm.nwritten)
-    atomicAdd((unsigned long long*)&ctl->n_written_nonid, (unsigned long long)sm.nwritten);
+  if (tid == 0) {
+    if (sm.nwritten) atomicAdd((unsigned long long*)&ctl->n_written_nonid, (unsigned long long)sm.nwritten);
+    if (sm.nabove) atomicAdd((unsigned long long*)&ctl->n_above_hi, (unsigned long long)sm.nabove);
+  }
 }
-
 
 // ---------------------------------------------------------------------------
 // rho = I: one identity string with coefficient 1 (Algorithm 1 initial state).
@@ -750,37 +907,103 @@ __global__ void init_kernel(Side s0, Plan* plan, Filter* filt, Ctl* ctl, int w0)
   *ctl = c;
 }
 
+// Parallel search, over a histogram of 2 * blockDim bins taken from the top,
+// for the bin where the running count from above first reaches `need`
+// (counts above the histogram: `base`).  Returns the bin (or -1) and the
+// count above it; all threads must call.
+__device__ inline void find_from_top(const uint32_t* h, int nbins, uint64_t base, uint64_t need,
+                                     uint64_t* s_scratch, int* out_bin, uint64_t* out_above) {
+  const int tid = threadIdx.x;
+  const int nth = blockDim.x;
+  const int per = (nbins + nth - 1) / nth;
+  // thread t owns bins nbins-1-t*per .. nbins-per-t*per (descending)
+  uint64_t local = 0;
+  for (int q = 0; q < per; ++q) {
+    const int b = nbins - 1 - (tid * per + q);
+    if (b >= 0) local += h[b];
+  }
+  s_scratch[tid] = local;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over threads (nth <= 1024)
+  for (int d = 1; d < nth; d <<= 1) {
+    const uint64_t v = (tid >= d) ? s_scratch[tid - d] : 0;
+    __syncthreads();
+    s_scratch[tid] += v;
+    __syncthreads();
+  }
+  uint64_t above = base + s_scratch[tid] - local;
+  for (int q = 0; q < per; ++q) {
+    const int b = nbins - 1 - (tid * per + q);
+    if (b < 0) break;
+    if (above < need && need <= above + h[b]) {
+      *out_bin = b;
+      *out_above = above;
+    }
+    above += h[b];
+  }
+  __syncthreads();
+}
+
 // After a gate: check the identity coefficient, decide whether the cap
-// binds and locate the histogram bin that holds the K-th value; prepare the
-// control block for the next gate.
-__global__ void select_decide(const Filter* filt_in, Filter* filt_out, Plan* plan_next, Ctl* ctl,
-                              int64_t K, int cap_fail) {
+// binds and which bit range of |c| holds the (K-1)-th largest non-identity
+// value; prepare the control block for the next gate.
+__global__ __launch_bounds__(1024) void select_decide(const Filter* filt_in, Filter* filt_out, Plan* plan_next,
+                                                      Ctl* ctl, int64_t K, int cap_fail) {
   __shared__ uint32_t h[kHistBins];
-  __shared__ uint32_t res_bin, res_need;
+  __shared__ uint32_t fh[kFineBins];
+  __shared__ uint64_t scr[1024];
+  __shared__ int s_bin;
+  __shared__ uint64_t s_above;
   const int tid = threadIdx.x;
   if (ctl->error) return;
   for (int i = tid; i < kHistBins; i += blockDim.x) h[i] = ctl->hist[i];
+  for (int i = tid; i < kFineBins; i += blockDim.x) fh[i] = ctl->fhist[i];
+  if (tid == 0) {
+    s_bin = -1;
+    s_above = 0;
+  }
   __syncthreads();
+  const Filter fin = *filt_in;
   const uint64_t nw = ctl->n_written_nonid + 1;  // identity included
   const bool capped = (int64_t)nw > K;
-  if (tid == 0) {
-    res_bin = 0;
-    res_need = 0;
-    if (capped) {
-      const uint64_t need = (uint64_t)(K - 1);
-      uint64_t cum = 0;
-      int b = kHistBins - 1;
-      for (; b >= 0; --b) {
-        if (cum + h[b] >= need) break;
-        cum += h[b];
+  const uint64_t need = (uint64_t)(K - 1);
+  uint64_t sel_lo = 0, sel_hi = 0, sel_need = 0;
+  bool none_kept = false;
+  if (capped && need == 0) {
+    none_kept = true;
+  } else if (capped) {
+    uint64_t win_lo = 0, win_hi = 0;
+    if (fin.cap_active) {
+      const double pred = __longlong_as_double((long long)fin.kth_bits) / fin.cI;
+      const uint64_t cb = abs_bits(pred);
+      win_lo = cb > kFineHalf ? cb - kFineHalf : 0;
+      win_hi = win_lo + 2 * kFineHalf;
+    }
+    const uint64_t nab = ctl->n_above_hi;
+    bool fine_ok = false;
+    if (win_hi > win_lo && nab < need) {
+      find_from_top(fh, kFineBins, nab, need, scr, &s_bin, &s_above);
+      if (s_bin >= 0) {
+        fine_ok = true;
+        sel_lo = win_lo + ((uint64_t)s_bin << kFineShift);
+        sel_hi = sel_lo + (1ull << kFineShift);
+        sel_need = need - s_above;
       }
-      if (b < 0) b = 0;
-      res_bin = (uint32_t)b;
-      res_need = (uint32_t)(need - cum);
+      __syncthreads();
+      if (tid == 0) s_bin = -1;
+      __syncthreads();
+    }
+    if (!fine_ok) {
+      find_from_top(h, kHistBins, 0, need, scr, &s_bin, &s_above);
+      const int b = s_bin < 0 ? 0 : s_bin;
+      sel_lo = b == 0 ? 0ull : ((uint64_t)(b + kHistBase) << kHistShift);
+      sel_hi = b == kHistBins - 1 ? ~0ull : ((uint64_t)(b + 1 + kHistBase) << kHistShift);
+      sel_need = need - (s_bin < 0 ? 0 : s_above);
     }
   }
   __syncthreads();
   for (int i = tid; i < kHistBins; i += blockDim.x) ctl->hist[i] = 0;
+  for (int i = tid; i < kFineBins; i += blockDim.x) ctl->fhist[i] = 0;
   if (tid < kMaxClasses * kMaxClasses) {
     plan_next->cnt[tid / kMaxClasses][tid % kMaxClasses] = 0;
     plan_next->ncnt[tid / kMaxClasses][tid % kMaxClasses] = 0;
@@ -795,28 +1018,32 @@ __global__ void select_decide(const Filter* filt_in, Filter* filt_out, Plan* pla
     f.cI = ctl->have_cI ? cI : 1.0;
     f.n_written = nw;
     f.cap_active = capped ? 1u : 0u;
-    f.kth_bits = 0;
+    f.kth_bits = none_kept ? 0x7fffffffffffffffull : 0ull;
     f.tie_active = 0;
     f.n_survivors = capped ? (uint64_t)K : nw;
     *filt_out = f;
-    ctl->term_updates += (double)filt_in->n_survivors;
+    ctl->term_updates += (double)fin.n_survivors;
+    ctl->alg_elems += (double)fin.n_survivors + (double)f.n_survivors;
     ctl->gates += 1;
     if (capped) ctl->cap_hit = 1;
-    ctl->sel_bin = res_bin;
-    ctl->sel_need = capped ? res_need : 0u;
+    ctl->sel_lo = sel_lo;
+    ctl->sel_hi = sel_hi;
+    ctl->sel_need = (capped && !none_kept) ? (uint32_t)sel_need : 0u;
     ctl->cand_count = 0;
     ctl->ticket = 0;
     ctl->n_written_nonid = 0;
+    ctl->n_above_hi = 0;
     ctl->have_cI = 0;
   }
 }
 
-// Collect the stored non-identity elements of the K-th value's bin.
+// Collect the stored non-identity elements whose |c| bits lie in the
+// selected range.
 template <int NW>
 __global__ void select_collect(Side out, const Plan* plan, Ctl* ctl, SelBuf sel) {
   if (ctl->error || ctl->sel_need == 0) return;
-  const uint32_t bin = ctl->sel_bin;
-  const Plan p = *plan;
+  const uint64_t lo = ctl->sel_lo, hi = ctl->sel_hi;
+  const Plan& p = *plan;
   const int nc = 1 << p.wc, ne = 1 << p.we;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (int c = 0; c < nc; ++c)
@@ -826,7 +1053,7 @@ __global__ void select_collect(Side out, const Plan* plan, Ctl* ctl, SelBuf sel)
       for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
         const uint64_t idx = base + i;
         const uint64_t b = abs_bits(out.coef[idx]);
-        if ((uint32_t)hist_bin(b) != bin) continue;
+        if (b < lo || b >= hi) continue;
         Key<NW> k = load_key<NW>(out, idx);
         if (key_zero(k)) continue;
         const unsigned long long slot = atomicAdd((unsigned long long*)&ctl->cand_count, 1ull);
@@ -846,52 +1073,43 @@ template <int NW>
 __global__ __launch_bounds__(1024) void select_exact(Side out, Filter* filt_out, Ctl* ctl, SelBuf sel,
                                                      RepPos rp) {
   __shared__ uint32_t h[2048];
-  __shared__ uint64_t s_prefix, s_mask;
-  __shared__ uint32_t s_need, s_digit, s_eq;
+  __shared__ uint64_t scr[1024];
+  __shared__ int s_bin;
+  __shared__ uint64_t s_above;
   __shared__ uint32_t s_cnt0;
   __shared__ unsigned long long s_ntie;
   if (ctl->error || ctl->sel_need == 0) return;
   const int tid = threadIdx.x;
   const uint64_t m = ctl->cand_count < sel.cap ? ctl->cand_count : sel.cap;
-  if (tid == 0) {
-    s_prefix = 0;
-    s_mask = 0;
-    s_need = ctl->sel_need;
-  }
-  __syncthreads();
+  uint64_t prefix = 0, mask = 0, need = ctl->sel_need;
+  uint32_t count_eq = 0;
   const int shifts[6] = {53, 42, 31, 20, 9, 0};
   const int widths[6] = {11, 11, 11, 11, 11, 9};
   for (int pass = 0; pass < 6; ++pass) {
     const int sh = shifts[pass];
-    const uint64_t dm = (1ull << widths[pass]) - 1ull;
+    const int nb = 1 << widths[pass];
+    const uint64_t dm = (uint64_t)nb - 1ull;
     for (int i = tid; i < 2048; i += blockDim.x) h[i] = 0;
+    if (tid == 0) {
+      s_bin = -1;
+      s_above = 0;
+    }
     __syncthreads();
-    const uint64_t pre = s_prefix, msk = s_mask;
     for (uint64_t i = tid; i < m; i += blockDim.x) {
       const uint64_t b = sel.cand_bits[i];
-      if ((b & msk) == pre) atomicAdd(&h[(b >> sh) & dm], 1u);
+      if ((b & mask) == prefix) atomicAdd(&h[(b >> sh) & dm], 1u);
     }
     __syncthreads();
-    if (tid == 0) {
-      uint32_t need = s_need;
-      uint32_t cum = 0;
-      int d = (int)dm;
-      for (; d >= 0; --d) {
-        if (cum + h[d] >= need) break;
-        cum += h[d];
-      }
-      if (d < 0) d = 0;
-      s_need = need - cum;
-      s_digit = (uint32_t)d;
-      s_eq = h[d];
-      s_prefix = pre | ((uint64_t)d << sh);
-      s_mask = msk | (dm << sh);
-    }
+    find_from_top(h, nb, 0, need, scr, &s_bin, &s_above);
+    const int d = s_bin < 0 ? 0 : s_bin;
+    need -= (s_bin < 0 ? 0 : s_above);
+    count_eq = h[d];
+    prefix |= (uint64_t)d << sh;
+    mask |= dm << sh;
     __syncthreads();
   }
-  const uint64_t kth = s_prefix;
-  const uint32_t need_eq = s_need;
-  const uint32_t count_eq = s_eq;
+  const uint64_t kth = prefix;
+  const uint32_t need_eq = (uint32_t)need;
   if (tid == 0) {
     filt_out->kth_bits = kth;
     filt_out->tie_active = 0;
@@ -914,7 +1132,7 @@ __global__ __launch_bounds__(1024) void select_exact(Side out, Filter* filt_out,
   const int n = rp.nbits / 2;
   Key<NW> pre, msk;
   for (int q = 0; q < NW; ++q) pre.w[q] = msk.w[q] = 0;
-  uint32_t need = need_eq;
+  uint32_t needk = need_eq;
   for (int part = 0; part < 2; ++part) {
     for (int qb = n - 1; qb >= 0; --qb) {
       const int word = part * W + (qb >> 6);
@@ -930,8 +1148,8 @@ __global__ __launch_bounds__(1024) void select_exact(Side out, Filter* filt_out,
       if (local) atomicAdd(&s_cnt0, local);
       __syncthreads();
       const uint32_t c0 = s_cnt0;
-      if (c0 < need) {
-        need -= c0;
+      if (c0 < needk) {
+        needk -= c0;
         pre.w[word] |= bit;
       }
       msk.w[word] |= bit;
@@ -959,7 +1177,7 @@ __global__ __launch_bounds__(256) void observe_kernel(Side s, const Plan* plan, 
                                                       const double* oc, int32_t m, double* result) {
   __shared__ double ssum[256], scmp[256];
   const int tid = threadIdx.x;
-  const Plan p = *plan;
+  const Plan& p = *plan;
   const Filter f = *filt;
   constexpr int W = NW / 2;
   const int n = rp.nbits / 2;
@@ -968,14 +1186,8 @@ __global__ __launch_bounds__(256) void observe_kernel(Side s, const Plan* plan, 
     Key<NW> k;
     for (int q = 0; q < NW; ++q) k.w[q] = 0;
     for (int qb = 0; qb < n; ++qb) {
-      if ((ox[(size_t)j * W + (qb >> 6)] >> (qb & 63)) & 1ull) {
-        const int pp = rp.pos[qb];
-        k.w[pp >> 6] |= 1ull << (pp & 63);
-      }
-      if ((oz[(size_t)j * W + (qb >> 6)] >> (qb & 63)) & 1ull) {
-        const int pp = rp.pos[n + qb];
-        k.w[pp >> 6] |= 1ull << (pp & 63);
-      }
+      if ((ox[(size_t)j * W + (qb >> 6)] >> (qb & 63)) & 1ull) xor_bit(k, rp.pos[qb], 1ull);
+      if ((oz[(size_t)j * W + (qb >> 6)] >> (qb & 63)) & 1ull) xor_bit(k, rp.pos[n + qb], 1ull);
     }
     const int e = class_of(k, rp.nbits, p.we);
     double a = 0.0;
@@ -1019,7 +1231,7 @@ __global__ __launch_bounds__(256) void observe_kernel(Side s, const Plan* plan, 
 template <int NW>
 __global__ void export_kernel(Side s, const Plan* plan, const Filter* filt, RepPos rp, uint64_t* ex,
                               uint64_t* ez, double* ec, unsigned long long* count, uint64_t limit) {
-  const Plan p = *plan;
+  const Plan& p = *plan;
   const Filter f = *filt;
   constexpr int W = NW / 2;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -1044,12 +1256,12 @@ __global__ void export_kernel(Side s, const Plan* plan, const Filter* filt, RepP
 
 // ---------------------------------------------------------------------------
 // Host launchers.
-constexpr int kBlock = 256;
+constexpr int kBlock = 512;
 template <int NW>
 struct TileFor;
 template <>
 struct TileFor<2> {
-  static constexpr int value = 1024;
+  static constexpr int value = 2048;
 };
 template <>
 struct TileFor<4> {
@@ -1067,14 +1279,20 @@ hipError_t launch_init(int nw, Side s0, Plan* plan, Filter* filt, Ctl* ctl, int 
 }
 
 hipError_t launch_gate(int nw, const GateParams& gp, Side in, Side out, const Plan* plan_in,
-                       Plan* plan_out, const Filter* filt_in, Ctl* ctl, TileStatus* status, int grid,
-                       hipStream_t st) {
-  if (nw == 2)
+                       Plan* plan_out, const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part,
+                       int grid, hipStream_t st) {
+  // one wavefront per tile boundary, four per block
+  const uint64_t nb = gp.status_cap + kMaxClasses;
+  const int pgrid = (int)((nb + 3) / 4);
+  if (nw == 2) {
+    hipLaunchKernelGGL(partition_kernel<2>, dim3(pgrid), dim3(256), 0, st, gp, in, plan_in, part, ctl);
     hipLaunchKernelGGL((gate_kernel<2, kBlock, TileFor<2>::value>), dim3(grid), dim3(kBlock), 0, st, gp,
-                       in, out, plan_in, plan_out, filt_in, ctl, status);
-  else
+                       in, out, plan_in, plan_out, filt_in, (const uint64_t*)part, ctl, status);
+  } else {
+    hipLaunchKernelGGL(partition_kernel<4>, dim3(pgrid), dim3(256), 0, st, gp, in, plan_in, part, ctl);
     hipLaunchKernelGGL((gate_kernel<4, kBlock, TileFor<4>::value>), dim3(grid), dim3(kBlock), 0, st, gp,
-                       in, out, plan_in, plan_out, filt_in, ctl, status);
+                       in, out, plan_in, plan_out, filt_in, (const uint64_t*)part, ctl, status);
+  }
   return hipGetLastError();
 }
 

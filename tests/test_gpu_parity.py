@@ -1,0 +1,226 @@
+"""GPU parity: the HIP engine against the CPU oracle, element by element.
+
+The FP64 path is bit-exact by construction (every output coefficient is at
+most one rounded product plus one rounded product, normalised by one IEEE
+division, in the same order as the oracle), so states are compared with
+``==`` on every coefficient.  Observables are compensated sums in both
+implementations and are compared to 1e-13 relative."""
+import math
+
+import numpy as np
+import pytest
+
+import itpp_workloads as W
+from oracle import c_oracle
+from oracle import itpp as OR
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2601_14400_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c_oracle.build(force=False)
+
+
+def gpu_state(w, steps=None, **kw):
+    e = P.engine_for(w, **kw)
+    st = e.evolve(w.dtau, w.n_steps if steps is None else steps)
+    S = e.state()
+    return e, st, S
+
+
+def assert_same_state(S_ref, S_gpu):
+    assert len(S_ref) == len(S_gpu)
+    diff = [k for k in S_ref if S_gpu.get(k) != S_ref[k]]
+    assert not diff, f"{len(diff)} coefficients differ, e.g. {diff[:3]} " \
+                     f"{[(S_ref[k], S_gpu.get(k)) for k in diff[:3]]}"
+
+
+def test_config1_bitexact_and_observables():
+    w = W.config1()
+    e, st, S = gpu_state(w)
+    o = c_oracle.run_workload(w)
+    ref = o.state()
+    assert_same_state(ref, S)
+    assert len(S) == math.comb(16, 8)
+    assert st["term_updates"] == o.term_updates()
+    assert st["n_gates"] == 320
+    for name, (strs, coefs) in w.observables.items():
+        g = e.expect(strs, coefs)
+        r = OR.expect(ref, strs, coefs)
+        assert abs(g - r) <= 1e-13 * max(1.0, abs(r)), name
+    e.close()
+
+
+def test_stepwise_prefixes_match_python_oracle():
+    w = W.config1()
+    e = P.engine_for(w)
+    S = {"I" * w.n: 1.0}
+    for step in range(4):
+        e.evolve(w.dtau, 1)
+        S, _ = OR.evolve(w.n, w.strings, w.alphas, w.schedule, w.dtau, 1, w.delta, w.K, S0=S)
+        assert_same_state(S, e.state())
+    e.close()
+
+
+def test_gatewise_prefixes():
+    """Stop after every elementary gate of the first step (evolve_gates)."""
+    w = W.tfim_workload("t", 6, 1.0, 0.8, True, 2, 0.05, 0.05, 1e-12, 1 << 16)
+    e = P.engine_for(w)
+    S = {"I" * w.n: 1.0}
+    for g, (k, m) in enumerate(w.schedule * 2):
+        e.evolve_gates(w.dtau, 1)
+        S, _ = OR.evolve(w.n, w.strings, w.alphas, [(k, m)], w.dtau, 1, w.delta, w.K, S0=S)
+        assert_same_state(S, e.state())
+    e.close()
+
+
+@pytest.mark.parametrize("n,terms,steps,seed", [(5, 9, 4, 0), (12, 14, 3, 1), (64, 20, 2, 2),
+                                                (100, 16, 2, 3), (128, 18, 2, 4)])
+def test_random_hamiltonians_with_y_bitexact(n, terms, steps, seed):
+    """Y terms, XZ terms and one- and two-word keys (n up to 128)."""
+    w = W.random_two_flip_workload("r", n, terms, seed, 0.1, steps, 1e-12, 1 << 20)
+    assert any("Y" in s for s in w.strings)
+    e, st, S = gpu_state(w)
+    ref = c_oracle.run_workload(w).state()
+    assert_same_state(ref, S)
+    e.close()
+
+
+@pytest.mark.parametrize("builder,steps", [
+    (lambda: W.config2(K=4096), 3),
+    (lambda: W.config3(K=4096, precision="f64"), 2),
+    (lambda: W.config5(K=4096), 3),
+    (lambda: W.config2(K=777), 2),
+])
+def test_capped_configs_bitexact(builder, steps):
+    """Workload shapes of the benchmark configs at a reduced cap: the exact
+    top-K selection with canonical tie-break runs on every gate."""
+    w = builder()
+    e, st, S = gpu_state(w, steps=steps)
+    o = c_oracle.run_workload(w, n_steps=steps)
+    assert_same_state(o.state(), S)
+    assert st["cap_hit"] == 1
+    assert len(S) == w.K
+    assert st["term_updates"] == o.term_updates()
+    e.close()
+
+
+def test_massive_ties_h0():
+    """h = 0: coefficients are exact powers tanh(beta J)^k, so the cap cuts
+    through large groups of equal values; the canonical tie-break decides."""
+    w = W.tfim_workload("t", 14, 1.0, 0.0, False, 1, 0.1, 0.6, 0.0, 200)
+    e, st, S = gpu_state(w)
+    ref, _ = OR.run_workload(w)
+    assert_same_state(ref, S)
+    e.close()
+
+
+def test_cap_one_keeps_identity():
+    w = W.tfim_workload("t", 8, 1.0, 1.0, True, 1, 0.05, 0.2, 1e-14, 1)
+    e, st, S = gpu_state(w)
+    assert S == {"I" * 8: 1.0}
+    e.close()
+
+
+def test_large_threshold_and_zero_steps():
+    w = W.tfim_workload("t", 8, 1.0, 1.0, True, 1, 0.05, 0.5, 0.3, 1 << 10)
+    e, st, S = gpu_state(w)
+    ref, _ = OR.run_workload(w)
+    assert_same_state(ref, S)
+    e.reset()
+    e.evolve(w.dtau, 0)
+    assert e.state() == {"I" * 8: 1.0}
+    assert e.expect(["XIIIIIII"], [1.0]) == 0.0
+    assert e.expect([], []) == 0.0
+    e.close()
+
+
+def test_continue_equals_single_run():
+    w = W.config2(K=2048)
+    e = P.engine_for(w)
+    e.evolve(w.dtau, 1)
+    e.evolve_gates(w.dtau, 7)
+    e.evolve_gates(w.dtau, len(w.schedule) - 7)
+    S1 = e.state()
+    e.reset()
+    e.evolve(w.dtau, 2)
+    assert e.state() == S1
+    e.close()
+
+
+def test_errors():
+    with pytest.raises(P.ItppError) as ex:
+        P.Engine(0, 1e-6, 10)
+    assert ex.value.status == 1
+    for bad in (dict(threshold=-1.0), dict(threshold=1.0), dict(threshold=float("nan")), dict(max_terms=0)):
+        kw = dict(n_qubits=8, threshold=1e-6, max_terms=10)
+        kw.update(bad)
+        with pytest.raises(P.ItppError) as ex:
+            P.Engine(**kw)
+        assert ex.value.status == 1
+    with pytest.raises(P.ItppError) as ex:
+        P.Engine(64, 1e-6, 1 << 24, device_bytes_limit=1 << 20)
+    assert ex.value.status == 2
+    e = P.Engine(8, 1e-6, 100)
+    with pytest.raises(P.ItppError):
+        e.evolve(0.1, 1)  # no Hamiltonian / schedule yet
+    with pytest.raises(P.ItppError) as ex:
+        e.set_hamiltonian(["XYIIIIII"], [1.0])  # flips three bits
+    assert ex.value.status == 1
+    with pytest.raises(P.ItppError):
+        e.set_hamiltonian(["XIIIIIII"], [float("inf")])
+    e.set_hamiltonian(["ZZIIIIII", "XIIIIIII"], [-1.0, -1.0])
+    with pytest.raises(P.ItppError):
+        e.set_schedule([(2, 1.0)])
+    e.set_schedule([(0, 1.0), (1, 1.0)])
+    with pytest.raises(P.ItppError):
+        e.evolve(0.0, 1)
+    with pytest.raises(P.ItppError):
+        e.evolve(-0.1, 1)
+    e.close()
+
+
+def test_cap_fail_policy():
+    w = W.config1()
+    e = P.Engine(w.n, w.delta, 100, cap_policy="fail")
+    e.set_hamiltonian(w.strings, w.alphas)
+    e.set_schedule(w.schedule)
+    with pytest.raises(P.ItppError) as ex:
+        e.evolve(w.dtau, 5)
+    assert ex.value.status == 3
+    e.reset()
+    e.evolve(w.dtau, 0)
+    assert e.num_terms() == 1
+    e.close()
+
+
+def test_identity_terms_are_skipped():
+    strings = ["IIII", "ZZII", "IXII"]
+    alphas = [0.7, -1.0, -0.5]
+    e = P.Engine(4, 0.0, 1 << 12)
+    e.set_hamiltonian(strings, alphas)
+    e.set_schedule([(0, 1.0), (1, 1.0), (2, 1.0)])
+    e.evolve(0.1, 3)
+    ref, _ = OR.evolve(4, strings, alphas, [(0, 1.0), (1, 1.0), (2, 1.0)], 0.1, 3, 0.0, 1 << 12)
+    assert_same_state(ref, e.state())
+    # <H> includes the identity weight
+    assert abs(e.expect(strings, alphas) - OR.expect(ref, strings, alphas)) < 1e-14
+    e.close()
+
+
+def test_export_canonical_and_unique():
+    w = W.config2(K=4096)
+    e = P.engine_for(w)
+    e.evolve(w.dtau, 2)
+    x, z, c = e.export()
+    keys = [(int(a[0]), int(b[0])) for a, b in zip(x, z)]
+    assert keys == sorted(keys)
+    assert len(set(keys)) == len(keys)
+    assert keys[0] == (0, 0) and c[0] == 1.0
+    e.close()
