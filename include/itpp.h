@@ -79,6 +79,8 @@ typedef struct {
   int32_t cap_hit;       /* 1 if the cap truncated at least one gate */
   int32_t reserved0;
   double alg_bytes;      /* sum over gates of (strings in + strings out) * (16W + 8) */
+  int64_t spec_gates;    /* gates that wrote only strings above a predicted cap margin */
+  int64_t spec_retries;  /* of those, gates redone because the prediction was too high */
 } itpp_stats;
 
 /* Kernel timing gathered with HIP events on the context's stream while
@@ -150,6 +152,15 @@ itpp_status itpp_num_terms(itpp_ctx ctx, int64_t* out);
  * *n_out receives the required capacity with ITPP_ERR_ARG. */
 itpp_status itpp_export(itpp_ctx ctx, int64_t capacity, uint64_t* x, uint64_t* z, double* coef,
                         int64_t* n_out);
+
+/* Engine options (results do not depend on them; only speed does).
+ *  ITPP_OPT_SPECULATION (default 1): once the cap binds, a gate writes only
+ *    the strings above a margin below the K-th value predicted from the
+ *    previous gate; if fewer than K-1 strings pass, the gate is redone
+ *    without the margin, so the kept set is always the exact one.
+ *  ITPP_OPT_SPEC_MARGIN (default 0.9): that margin as a factor in (0, 1]. */
+typedef enum { ITPP_OPT_SPECULATION = 1, ITPP_OPT_SPEC_MARGIN = 2 } itpp_option;
+itpp_status itpp_set_option(itpp_ctx ctx, int32_t option, double value);
 
 /* Enable (1) or disable (0) per-gate HIP event timing; enabling clears the
  * accumulated figures.  Timing adds two event records per gate. */

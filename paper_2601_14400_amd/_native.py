@@ -22,7 +22,7 @@ STATUS = {0: "ITPP_OK", 1: "ITPP_ERR_ARG", 2: "ITPP_ERR_OOM", 3: "ITPP_ERR_CAP",
 # Every entry point declared in include/itpp.h.
 EXPORTED = ["itpp_create", "itpp_destroy", "itpp_set_hamiltonian", "itpp_set_schedule",
             "itpp_reset", "itpp_evolve", "itpp_evolve_gates", "itpp_expect", "itpp_num_terms", "itpp_export",
-            "itpp_set_timing", "itpp_get_timing", "itpp_last_error", "itpp_version"]
+            "itpp_set_option", "itpp_set_timing", "itpp_get_timing", "itpp_last_error", "itpp_version"]
 
 
 class ItppConfig(ctypes.Structure):
@@ -36,7 +36,8 @@ class ItppStats(ctypes.Structure):
     _fields_ = [("n_terms", ctypes.c_int64), ("n_gates", ctypes.c_int64),
                 ("term_updates", ctypes.c_double), ("c_identity", ctypes.c_double),
                 ("cap_hit", ctypes.c_int32), ("reserved0", ctypes.c_int32),
-                ("alg_bytes", ctypes.c_double)]
+                ("alg_bytes", ctypes.c_double), ("spec_gates", ctypes.c_int64),
+                ("spec_retries", ctypes.c_int64)]
 
 
 class ItppTiming(ctypes.Structure):
@@ -80,6 +81,7 @@ def load_library(path: Optional[str] = None):
     lib.itpp_expect.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(dbl)]
     lib.itpp_num_terms.argtypes = [vp, ctypes.POINTER(i64)]
     lib.itpp_export.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(i64)]
+    lib.itpp_set_option.argtypes = [vp, i32, dbl]
     lib.itpp_set_timing.argtypes = [vp, i32]
     lib.itpp_get_timing.argtypes = [vp, ctypes.POINTER(ItppTiming)]
     lib.itpp_last_error.argtypes = [vp]
@@ -203,7 +205,12 @@ class Engine:
     @staticmethod
     def _stats(st):
         return {"n_terms": st.n_terms, "n_gates": st.n_gates, "term_updates": st.term_updates,
-                "c_identity": st.c_identity, "cap_hit": st.cap_hit, "alg_bytes": st.alg_bytes}
+                "c_identity": st.c_identity, "cap_hit": st.cap_hit, "alg_bytes": st.alg_bytes,
+                "spec_gates": st.spec_gates, "spec_retries": st.spec_retries}
+
+    def set_option(self, name: str, value: float):
+        opt = {"speculation": 1, "spec_margin": 2}[name]
+        self._check(self._lib.itpp_set_option(self._h, opt, float(value)))
 
     def set_timing(self, enable: bool = True):
         self._check(self._lib.itpp_set_timing(self._h, 1 if enable else 0))

@@ -66,6 +66,10 @@ struct itpp_ctx_s {
   int par = 0;           // plan/filter slot describing the stored state
   bool ready = false;
   uint32_t epoch = 1;
+  uint64_t serial = 1;
+  bool speculate = true;
+  double spec_mult = 0.9;
+  int64_t retries_total = 0;
   std::string err;
   // timing
   bool timing = false;
@@ -77,7 +81,9 @@ struct itpp_ctx_s {
 
 namespace {
 
-const char* kVersion = "itpp gfx950 merge-join engine 0.1";
+const char* kVersion = "itpp gfx950 merge-join engine 0.2";
+// Host synchronisation period (gates) for the speculation check.
+constexpr int64_t kSyncEvery = 512;
 thread_local std::string g_create_error = "no error";
 
 itpp_status create_fail(itpp_status s, const std::string& m) {
@@ -402,12 +408,108 @@ itpp_status itpp_evolve_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_sta
   return run_gates(c, dtau, n_gates, st);
 }
 
+// Plan and enqueue the next elementary gate of the schedule (asynchronous).
+static itpp_status enqueue_gate(itpp_ctx c, double dtau, bool spec) {
+  const int G = (int)c->glist.size();
+  const int nbits = c->nbits;
+  const int i = c->gpos;
+  const int sg = c->glist[i];
+  const TermInfo& t = c->terms[c->sched_term[sg]];
+  const TermInfo& t1 = c->terms[c->sched_term[c->glist[(i + 1) % G]]];
+  const TermInfo& t2 = c->terms[c->sched_term[c->glist[(i + 2) % G]]];
+  const double theta = t.alpha * c->sched_mult[sg] * dtau;
+  GateParams gp;
+  std::memset(&gp, 0, sizeof(gp));
+  gp.ch = std::cosh(theta);
+  gp.sh = std::sinh(theta);
+  gp.nbits = nbits;
+  gp.w = (int)t.F.size();
+  gp.w1 = (int)t1.F.size();
+  gp.w2 = (int)t2.F.size();
+  for (int b : t.cbits) {
+    const int p = c->pos[b];
+    gp.cmask[p >> 6] |= 1ull << (p & 63);
+  }
+  gp.nsup = t.nsup;
+  gp.aQ = t.aQ & 3;
+  for (int j = 0; j < t.nsup; ++j) {
+    gp.px[j] = c->pos[t.sup[j]];
+    gp.pz[j] = c->pos[c->n + t.sup[j]];
+    gp.qx[j] = t.qx[j];
+    gp.qz[j] = t.qz[j];
+  }
+  for (int k = 0; k < gp.w; ++k)
+    if (c->pos[t.F[k]] != nbits - gp.w + k) return fail(c, ITPP_ERR_DEVICE, "internal error: rep invariant");
+  std::vector<int> pos1 = c->pos;
+  for (int m = 0; m < gp.w1; ++m) {
+    gp.epos[m] = c->pos[t1.F[m]];
+    move_top(pos1, t1.F[m], nbits, &gp.mv[m]);
+  }
+  gp.ov = 0;
+  for (int k = 0; k < gp.w1; ++k)
+    if (std::find(t.F.begin(), t.F.end(), t1.F[k]) != t.F.end()) gp.ov |= 1 << k;
+  gp.ovf = 0;
+  for (int b = 0; b < gp.w2; ++b) {
+    gp.fpos[b] = pos1[t2.F[b]];
+    gp.fposg[b] = c->pos[t2.F[b]];
+    if (std::find(t.F.begin(), t.F.end(), t2.F[b]) != t.F.end()) gp.ovf |= 1 << b;
+  }
+  for (int k = 0; k < gp.w; ++k) {
+    const int q = pos1[t.F[k]];
+    gp.qm1[q >> 6] |= 1ull << (q & 63);
+  }
+  gp.tile = gate_tile(c->NW);
+  gp.epoch = c->epoch;
+  c->epoch = (c->epoch + 1) & 0x3fffffffu;
+  if (c->epoch == 0) c->epoch = 1;
+  gp.delta = c->cfg.threshold;
+  gp.cap_elems = c->cap;
+  gp.status_cap = c->status_cap;
+  gp.spec = spec ? 1 : 0;
+  gp.spec_mult = c->spec_mult;
+  gp.serial = c->serial++;
+  for (int b = 0; b < nbits; ++b) gp.pos_in[b] = (uint8_t)c->pos[b];
+  RepPos rp{};
+  rp.nbits = nbits;
+  for (int b = 0; b < nbits; ++b) rp.pos[b] = (uint8_t)pos1[b];
+  const int in = c->cur, out = c->cur ^ 1;
+  const int pin = c->par, pout = c->par ^ 1;
+  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+  if (c->timing) {
+    if (c->ev_used + 3 > 3 * 4096) HIP_TRY(c, drain_events(c));
+    HIP_TRY(c, next_event(c, &e0));
+    HIP_TRY(c, next_event(c, &e1));
+    HIP_TRY(c, next_event(c, &e2));
+    HIP_TRY(c, hipEventRecord(e0, c->stream));
+  }
+  HIP_TRY(c, launch_gate(c->NW, gp, c->side[in], c->side[out], c->plan + pin, c->plan + pout, c->filt + pin,
+                         c->ctl, c->status, c->part, c->cus * 2, c->stream));
+  if (c->timing) HIP_TRY(c, hipEventRecord(e1, c->stream));
+  HIP_TRY(c, launch_select(c->NW, c->side[out], c->plan + pout, c->filt + pin, c->filt + pout, c->plan + pin,
+                           c->ctl, c->sel, rp, c->cfg.max_terms, c->cfg.cap_policy == ITPP_CAP_FAIL ? 1 : 0,
+                           gp.spec, gp.serial, c->cus * 4, c->stream));
+  if (c->timing) HIP_TRY(c, hipEventRecord(e2, c->stream));
+  c->pos.swap(pos1);
+  c->cur = out;
+  c->par = pout;
+  c->gpos = (i + 1) % G;
+  return ITPP_OK;
+}
+
+namespace {
+struct HostSnap {
+  std::vector<int> pos;
+  int cur, par, gpos;
+  uint64_t serial;
+  size_t ev_used;
+};
+}  // namespace
+
 static itpp_status run_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stats* st) {
   if (!c->ready) {
     itpp_status s = do_reset(c);
     if (s != ITPP_OK) return s;
   }
-  // zero the run statistics
   Ctl h0{};
   HIP_TRY(c, hipMemcpyAsync(&h0, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -415,83 +517,49 @@ static itpp_status run_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stat
   const double tu0 = h0.term_updates;
   const double ae0 = h0.alg_elems;
   const uint64_t g0 = h0.gates;
+  const uint64_t sg0 = h0.spec_gates;
   const int G = (int)c->glist.size();
-  const int grid = c->cus * 2;
-  const int sel_grid = c->cus * 4;
-  const int tile = gate_tile(c->NW);
-  const int nbits = c->nbits;
-  GateParams gp{};
-  RepPos rp{};
-  rp.nbits = nbits;
-  for (int64_t gi = 0; gi < n_gates && G > 0; ++gi) {
-    {
-      const int i = c->gpos;
-      const int sg = c->glist[i];
-      const TermInfo& t = c->terms[c->sched_term[sg]];
-      const TermInfo& t1 = c->terms[c->sched_term[c->glist[(i + 1) % G]]];
-      const TermInfo& t2 = c->terms[c->sched_term[c->glist[(i + 2) % G]]];
-      const double theta = t.alpha * c->sched_mult[sg] * dtau;
-      std::memset(&gp, 0, sizeof(gp));
-      gp.ch = std::cosh(theta);
-      gp.sh = std::sinh(theta);
-      gp.nbits = nbits;
-      gp.w = (int)t.F.size();
-      gp.w1 = (int)t1.F.size();
-      gp.w2 = (int)t2.F.size();
-      for (int b : t.cbits) {
-        const int p = c->pos[b];
-        gp.cmask[p >> 6] |= 1ull << (p & 63);
-      }
-      gp.nsup = t.nsup;
-      gp.aQ = t.aQ & 3;
-      for (int j = 0; j < t.nsup; ++j) {
-        gp.px[j] = c->pos[t.sup[j]];
-        gp.pz[j] = c->pos[c->n + t.sup[j]];
-        gp.qx[j] = t.qx[j];
-        gp.qz[j] = t.qz[j];
-      }
-      for (int k = 0; k < gp.w; ++k)
-        if (c->pos[t.F[k]] != nbits - gp.w + k) return fail(c, ITPP_ERR_DEVICE, "internal error: rep invariant");
-      std::vector<int> pos1 = c->pos;
-      for (int m = 0; m < gp.w1; ++m) move_top(pos1, t1.F[m], nbits, &gp.mv[m]);
-      for (int b = 0; b < gp.w2; ++b) gp.fpos[b] = pos1[t2.F[b]];
-      gp.ov = 0;
-      for (int k = 0; k < gp.w1; ++k)
-        if (std::find(t.F.begin(), t.F.end(), t1.F[k]) != t.F.end()) gp.ov |= 1 << k;
-      gp.tile = tile;
-      gp.epoch = c->epoch;
-      c->epoch = (c->epoch + 1) & 0x3fffffffu;
-      if (c->epoch == 0) c->epoch = 1;
-      gp.delta = c->cfg.threshold;
-      gp.cap_elems = c->cap;
-      gp.status_cap = c->status_cap;
-      for (int b = 0; b < nbits; ++b) gp.pos_in[b] = (uint8_t)c->pos[b];
-      for (int b = 0; b < nbits; ++b) rp.pos[b] = (uint8_t)pos1[b];
-      const int in = c->cur, out = c->cur ^ 1;
-      const int pin = c->par, pout = c->par ^ 1;
-      hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
-      if (c->timing) {
-        if (c->ev_used + 3 > 3 * 4096) HIP_TRY(c, drain_events(c));
-        HIP_TRY(c, next_event(c, &e0));
-        HIP_TRY(c, next_event(c, &e1));
-        HIP_TRY(c, next_event(c, &e2));
-        HIP_TRY(c, hipEventRecord(e0, c->stream));
-      }
-      HIP_TRY(c, launch_gate(c->NW, gp, c->side[in], c->side[out], c->plan + pin, c->plan + pout,
-                             c->filt + pin, c->ctl, c->status, c->part, grid, c->stream));
-      if (c->timing) HIP_TRY(c, hipEventRecord(e1, c->stream));
-      HIP_TRY(c, launch_select(c->NW, c->side[out], c->plan + pout, c->filt + pin, c->filt + pout,
-                               c->plan + pin, c->ctl, c->sel, rp, c->cfg.max_terms,
-                               c->cfg.cap_policy == ITPP_CAP_FAIL ? 1 : 0, sel_grid, c->stream));
-      if (c->timing) HIP_TRY(c, hipEventRecord(e2, c->stream));
-      c->pos.swap(pos1);
-      c->cur = out;
-      c->par = pout;
-      c->gpos = (i + 1) % G;
+  int64_t retries = 0;
+  int64_t done = 0;
+  bool nospec_next = false;
+  std::vector<HostSnap> snaps;
+  // Gates are enqueued in batches; after each batch the host checks whether
+  // a speculative gate asked to be redone (all kernels after it were no-ops,
+  // so that gate's input is intact) and replays from there without
+  // speculation for that gate.
+  while (done < n_gates && G > 0) {
+    const int64_t batch = std::min<int64_t>(n_gates - done, kSyncEvery);
+    snaps.clear();
+    for (int64_t b = 0; b < batch; ++b) {
+      snaps.push_back(HostSnap{c->pos, c->cur, c->par, c->gpos, c->serial, c->ev_used});
+      const bool spec = c->speculate && !(b == 0 && nospec_next);
+      itpp_status s = enqueue_gate(c, dtau, spec);
+      if (s != ITPP_OK) return s;
     }
+    nospec_next = false;
+    Ctl h{};
+    HIP_TRY(c, hipMemcpyAsync(&h, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (h.error) return check_error(c);
+    if (h.halt) {
+      const int64_t idx = (int64_t)(h.halt_serial - snaps[0].serial);
+      if (idx < 0 || idx >= batch) return fail(c, ITPP_ERR_DEVICE, "internal error: bad retry serial");
+      const HostSnap& sn = snaps[idx];
+      c->pos = sn.pos;
+      c->cur = sn.cur;
+      c->par = sn.par;
+      c->gpos = sn.gpos;
+      // keep the timing of the failed attempt, drop the no-op launches after it
+      if (c->timing) c->ev_used = std::min(c->ev_used, sn.ev_used + 3);
+      HIP_TRY(c, launch_prepare(c->plan + (c->par ^ 1), c->ctl, c->stream));
+      done += idx;
+      nospec_next = true;
+      ++retries;
+      continue;
+    }
+    done += batch;
   }
-  itpp_status s = check_error(c);
-  if (s != ITPP_OK) return s;
+  c->retries_total += retries;
   if (st) {
     Ctl h{};
     Filter f{};
@@ -504,6 +572,8 @@ static itpp_status run_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stat
     st->c_identity = f.cI;
     st->cap_hit = (int32_t)h.cap_hit;
     st->alg_bytes = (h.alg_elems - ae0) * (double)(8 * c->NW + 8);
+    st->spec_gates = (int64_t)(h.spec_gates - sg0);
+    st->spec_retries = retries;
   }
   if (c->timing) {
     Ctl h{};
@@ -512,6 +582,22 @@ static itpp_status run_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stat
     c->t_alg_bytes += (h.alg_elems - ae0) * (double)(8 * c->NW + 8);
   }
   return ITPP_OK;
+}
+
+itpp_status itpp_set_option(itpp_ctx c, int32_t option, double value) {
+  if (!c) return ITPP_ERR_ARG;
+  switch (option) {
+    case ITPP_OPT_SPECULATION:
+      if (value != 0.0 && value != 1.0) return fail(c, ITPP_ERR_ARG, "speculation must be 0 or 1");
+      c->speculate = value != 0.0;
+      return ITPP_OK;
+    case ITPP_OPT_SPEC_MARGIN:
+      if (!(value > 0.0) || !(value <= 1.0)) return fail(c, ITPP_ERR_ARG, "margin must be in (0, 1]");
+      c->spec_mult = value;
+      return ITPP_OK;
+    default:
+      return fail(c, ITPP_ERR_ARG, "unknown option");
+  }
 }
 
 itpp_status itpp_set_timing(itpp_ctx c, int32_t enable) {

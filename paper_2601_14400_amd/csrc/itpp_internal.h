@@ -53,6 +53,7 @@ struct Filter {
   uint64_t tie_key[kMaxKeyWords];  // canonical key (x words, then z words) of the last tied survivor
   uint64_t n_written;        // stored elements (identity included)
   uint64_t n_survivors;      // elements that pass the filter
+  uint64_t ref_bits;         // |c| bits near which the next gate's K-th value is expected (0: none)
 };
 
 // Per-run control block (device).
@@ -70,11 +71,15 @@ struct Ctl {
   uint32_t sel_need;         // elements still needed from that range
   uint32_t pad2;
   uint64_t cand_count;
+  uint32_t need_coarse;      // the fine window missed: select from a full histogram
+  uint32_t pad3;
   double term_updates;
   double alg_elems;          // sum over gates of survivors in + survivors out
   uint64_t gates;
   uint32_t cap_hit;
-  uint32_t pad;
+  uint32_t halt;             // 1: a speculative gate must be redone; later kernels do nothing
+  uint64_t halt_serial;      // serial of that gate
+  uint64_t spec_gates;       // gates that ran with a speculative write threshold
 };
 
 enum : uint32_t {
@@ -123,6 +128,13 @@ struct GateParams {
   int32_t mv[kMaxClassBits];     // rep positions (sequential) moved to the top for the next gate
   int32_t fpos[kMaxClassBits];   // positions, in the next rep, of the bits of the gate after next
   int32_t ov;                // pattern over the next gate's bits flipped by this gate
+  int32_t epos[kMaxClassBits];   // positions, in this rep, of the next gate's flip bits (class bits)
+  int32_t fposg[kMaxClassBits];  // positions, in this rep, of the flip bits of the gate after next
+  int32_t ovf;               // pattern over the latter bits flipped by this gate
+  int32_t spec;              // 1: write only outputs above a margin below the predicted K-th value
+  uint64_t qm1[kMaxKeyWords];    // this gate's flip mask in the next rep (branch key = self key ^ qm1)
+  double spec_mult;          // that margin as a factor of the predicted value
+  uint64_t serial;           // host serial number of this gate launch
   int32_t tile;              // merged elements per tile
   uint32_t epoch;            // unique per launched gate (look-back tags)
   uint32_t check_write_threshold;
@@ -147,7 +159,8 @@ hipError_t launch_gate(int nw, const GateParams& gp, Side in, Side out, const Pl
                        int grid, hipStream_t st);
 hipError_t launch_select(int nw, Side out, const Plan* plan_out, const Filter* filt_in,
                          Filter* filt_out, Plan* plan_next, Ctl* ctl, SelBuf sel, const RepPos& rp,
-                         int64_t K, int cap_fail, int grid, hipStream_t st);
+                         int64_t K, int cap_fail, int spec, uint64_t serial, int grid, hipStream_t st);
+hipError_t launch_prepare(Plan* plan_out, Ctl* ctl, hipStream_t st);
 hipError_t launch_observe(int nw, Side s, const Plan* plan, const Filter* filt, const RepPos& rp,
                           const uint64_t* ox, const uint64_t* oz, const double* oc, int32_t m,
                           double* result, Ctl* ctl, hipStream_t st);

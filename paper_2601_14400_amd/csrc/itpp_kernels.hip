@@ -342,7 +342,7 @@ __global__ __launch_bounds__(256) void partition_kernel(GateParams gp, Side in, 
   __shared__ JoinLayout L;
   if (threadIdx.x == 0) make_layout(L, plan_in, gp.w, gp.tile);
   __syncthreads();
-  if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kErrNone) return;
+  if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kErrNone || ctl->halt) return;
   const int lane = threadIdx.x & 63;
   const uint64_t b = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   // boundary b -> join j, local boundary tl (join j owns tiles_before[j]+j .. tiles_before[j+1]+j)
@@ -423,7 +423,6 @@ struct GateSmem {
   uint16_t rs[CAPT], rb[CAPT];  // ranks of the self / branch output inside the tile's stream and class
   uint64_t tot0, tot1;          // tile totals per next class (16-bit lanes): stream cA, stream cB
   uint64_t wa[BLOCK / 64], wb[BLOCK / 64];
-  uint32_t hist[kHistBins];
   uint32_t fhist[kFineBins];
   uint32_t ncnt[kMaxClasses * kMaxClasses];
   uint64_t out_base[kMaxClasses + 1][kMaxClasses];  // row kMaxClasses holds the total
@@ -453,18 +452,14 @@ __device__ __forceinline__ Key<NW> lds_key(const uint64_t (*key)[TILE + 2], int 
 }
 
 // New value of an element (Eq. ITPP_PropRules, then the branch of an
-// unpaired commuting string).
-template <int NW>
-__device__ __forceinline__ void element_values(const Key<NW>& own, double c, bool comm, bool paired, double cp,
-                                               const GateParams& gp, Ctl* ctl, double& vs, double& vb) {
+// unpaired commuting string); neg: Q P = -R.
+__device__ __forceinline__ void values_from(double c, bool comm, bool paired, double cp, bool neg,
+                                            const GateParams& gp, double& vs, double& vb) {
   vb = 0.0;
   if (!comm) {
     vs = c;
     return;
   }
-  const int e4 = phase_negative(own, gp);
-  if (e4 & 1) atomicMax(&ctl->error, kErrPhase);
-  const bool neg = (e4 == 2);  // Q P = -R
   const double t1 = __dmul_rn(gp.ch, c);
   if (paired) {
     double t2 = __dmul_rn(gp.sh, cp);
@@ -491,6 +486,8 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
   __shared__ Smem sm;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
+  // nothing at all (not even the plan prologue) after an error or a halt
+  if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kErrNone || ctl->halt) return;
   const Filter fin = *filt_in;
   const int nbits = gp.nbits;
   const int w = gp.w;
@@ -499,14 +496,18 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
   const int ncls1 = 1 << gp.w1;
   // fine histogram window around the value predicted from the previous cap
   uint64_t win_lo = 0, win_hi = 0;
-  if (fin.cap_active) {
-    const double pred = __longlong_as_double((long long)fin.kth_bits) / fin.cI;
+  double tw = gp.delta;  // outputs are written when |v| > tw
+  if (fin.ref_bits) {
+    const double pred = __longlong_as_double((long long)fin.ref_bits) / fin.cI;
     const uint64_t cb = abs_bits(pred);
     win_lo = cb > kFineHalf ? cb - kFineHalf : 0;
     win_hi = win_lo + 2 * kFineHalf;
+    if (gp.spec && fin.cap_active) {
+      const double t = __dmul_rn(pred, gp.spec_mult);
+      tw = t > tw ? t : tw;
+    }
   }
 
-  for (int i = tid; i < kHistBins; i += BLOCK) sm.hist[i] = 0;
   for (int i = tid; i < kFineBins; i += BLOCK) sm.fhist[i] = 0;
   if (tid < kMaxClasses * kMaxClasses) sm.ncnt[tid] = 0;
   if (tid == 0) {
@@ -532,7 +533,7 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
   }
   __syncthreads();
   const uint64_t total_tiles = sm.L.tiles_before[sm.L.njoin];
-  if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kErrNone) return;
+  if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kErrNone || ctl->halt) return;
 
   for (;;) {
     if (tid == 0) sm.tile = atomicAdd(&ctl->ticket, 1u);
@@ -625,28 +626,31 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
               const double cp = paired ? sm.coef[y] : 0.0;
               const Key<NW> k = isA ? ka : kb;
               const Key<NW> ownk = isA ? k : xor_top(k, nbits, w);
-              const Key<NW> brk = isA ? xor_top(k, nbits, w) : k;
+              bool neg = false;
+              if (comm) {
+                const int e4 = phase_negative(ownk, gp);
+                if (e4 & 1) atomicMax(&ctl->error, kErrPhase);
+                neg = (e4 == 2);
+                if (neg) inf |= 512u;
+              }
               double vs, vb;
-              element_values(ownk, c, comm, paired, cp, gp, ctl, vs, vb);
-              const bool hs = fabs(vs) > gp.delta;
-              const bool hb = comm && !paired && fabs(vb) > gp.delta;
+              values_from(c, comm, paired, cp, neg, gp, vs, vb);
+              const bool hs = fabs(vs) > tw;
+              const bool hb = comm && !paired && fabs(vb) > tw;
               if (paired) {
                 inf |= 4u;
                 sm.partner[x] = (uint16_t)y;
               }
+              int es = 0;
+              for (int mm = 0; mm < gp.w1; ++mm) es |= get_bit(ownk, gp.epos[mm]) << mm;
               if (hs) {
-                Key<NW> ks = ownk;
-                for (int mm = 0; mm < gp.w1; ++mm) ks = move_top(ks, gp.mv[mm], nbits);
-                const int es = class_of(ks, nbits, gp.w1);
                 inf |= (uint16_t)(8u | (es << 4));
                 uint64_t& cc = isA ? c0 : c1;
                 rsx = (uint16_t)lane16(cc, es);
                 cc += 1ull << (16 * es);
               }
               if (hb) {
-                Key<NW> kk = brk;
-                for (int mm = 0; mm < gp.w1; ++mm) kk = move_top(kk, gp.mv[mm], nbits);
-                const int eb = class_of(kk, nbits, gp.w1);
+                const int eb = es ^ gp.ov;  // the branch differs in this gate's bits only
                 inf |= (uint16_t)(64u | (eb << 7));
                 uint64_t& cc = isA ? c1 : c0;
                 rbx = (uint16_t)lane16(cc, eb);
@@ -803,18 +807,25 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
       if (!(inf & (8u | 64u))) continue;
       const bool isA = x < nAt;
       const Key<NW> k = lds_key<NW, TILE>(sm.key, x);
-      const Key<NW> ownk = isA ? k : xor_top(k, nbits, w);
       const bool paired = (inf >> 2) & 1;
       double vs, vb;
-      element_values(ownk, sm.coef[x], (inf >> 1) & 1, paired, paired ? sm.coef[sm.partner[x]] : 0.0, gp, ctl,
-                     vs, vb);
+      values_from(sm.coef[x], (inf >> 1) & 1, paired, paired ? sm.coef[sm.partner[x]] : 0.0, (inf >> 9) & 1, gp,
+                  vs, vb);
+      // next-rep keys: one bit move; the two outputs differ by this gate's mask
+      Key<NW> mk = k;
+      for (int mm = 0; mm < gp.w1; ++mm) mk = move_top(mk, gp.mv[mm], nbits);
+      Key<NW> mq = mk;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) mq.w[q] ^= gp.qm1[q];
+      const Key<NW> ownk = isA ? k : xor_top(k, nbits, w);
+      int fself = 0;
+      for (int bq = 0; bq < gp.w2; ++bq) fself |= get_bit(ownk, gp.fposg[bq]) << bq;
       if (inf & 8u) {
         const int es = (inf >> 4) & 3;
         const int stream = isA ? 0 : 1;
         const int cls = isA ? cA : cB;
         const uint64_t pos = sm.out_base[cls][es] + sm.excl[stream * kMaxClasses + es] + sm.rs[x];
-        Key<NW> ks = ownk;
-        for (int mm = 0; mm < gp.w1; ++mm) ks = move_top(ks, gp.mv[mm], nbits);
+        const Key<NW>& ks = isA ? mk : mq;
         if (pos >= region_end(sm.out_base, cls, es)) {
           atomicMax(&ctl->error, kErrCapacity);
         } else {
@@ -825,14 +836,11 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
             ctl->have_cI = 1u;
           } else {
             const uint64_t bits = abs_bits(vs);
-            atomicAdd(&sm.hist[hist_bin(bits)], 1u);
             if (bits >= win_hi) ++above;
             else if (bits >= win_lo) atomicAdd(&sm.fhist[(bits - win_lo) >> kFineShift], 1u);
             ++written;
           }
-          int f = 0;
-          for (int bq = 0; bq < gp.w2; ++bq) f |= get_bit(ks, gp.fpos[bq]) << bq;
-          atomicAdd(&sm.ncnt[es * kMaxClasses + f], 1u);
+          atomicAdd(&sm.ncnt[es * kMaxClasses + fself], 1u);
         }
       }
       if (inf & 64u) {
@@ -840,21 +848,17 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
         const int stream = isA ? 1 : 0;
         const int cls = isA ? cB : cA;
         const uint64_t pos = sm.out_base[cls][eb] + sm.excl[stream * kMaxClasses + eb] + sm.rb[x];
-        Key<NW> kb = isA ? xor_top(k, nbits, w) : k;
-        for (int mm = 0; mm < gp.w1; ++mm) kb = move_top(kb, gp.mv[mm], nbits);
+        const Key<NW>& kb = isA ? mq : mk;
         if (pos >= region_end(sm.out_base, cls, eb)) {
           atomicMax(&ctl->error, kErrCapacity);
         } else {
           store_key<NW>(out, pos, kb);
           out.coef[pos] = vb;
           const uint64_t bits = abs_bits(vb);
-          atomicAdd(&sm.hist[hist_bin(bits)], 1u);
           if (bits >= win_hi) ++above;
           else if (bits >= win_lo) atomicAdd(&sm.fhist[(bits - win_lo) >> kFineShift], 1u);
           ++written;
-          int f = 0;
-          for (int bq = 0; bq < gp.w2; ++bq) f |= get_bit(kb, gp.fpos[bq]) << bq;
-          atomicAdd(&sm.ncnt[eb * kMaxClasses + f], 1u);
+          atomicAdd(&sm.ncnt[eb * kMaxClasses + (fself ^ gp.ovf)], 1u);
         }
       }
     }
@@ -864,10 +868,6 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
   }
   // flush per-workgroup statistics
   __syncthreads();
-  for (int i = tid; i < kHistBins; i += BLOCK) {
-    const uint32_t v = sm.hist[i];
-    if (v) atomicAdd(&ctl->hist[i], v);
-  }
   if (win_hi > win_lo)
     for (int i = tid; i < kFineBins; i += BLOCK) {
       const uint32_t v = sm.fhist[i];
@@ -948,15 +948,27 @@ __device__ inline void find_from_top(const uint32_t* h, int nbins, uint64_t base
 // binds and which bit range of |c| holds the (K-1)-th largest non-identity
 // value; prepare the control block for the next gate.
 __global__ __launch_bounds__(1024) void select_decide(const Filter* filt_in, Filter* filt_out, Plan* plan_next,
-                                                      Ctl* ctl, int64_t K, int cap_fail) {
-  __shared__ uint32_t h[kHistBins];
+                                                      Ctl* ctl, int64_t K, int cap_fail, int spec,
+                                                      uint64_t serial) {
   __shared__ uint32_t fh[kFineBins];
   __shared__ uint64_t scr[1024];
   __shared__ int s_bin;
   __shared__ uint64_t s_above;
   const int tid = threadIdx.x;
-  if (ctl->error) return;
-  for (int i = tid; i < kHistBins; i += blockDim.x) h[i] = ctl->hist[i];
+  if (ctl->error || ctl->halt) return;
+  {
+    // a speculative gate that wrote fewer than K-1 strings above its write
+    // threshold cannot decide the cap exactly: ask the host to redo it
+    const Filter& f0 = *filt_in;
+    if (spec && f0.cap_active && (int64_t)ctl->n_written_nonid < K - 1) {
+      __syncthreads();
+      if (tid == 0) {
+        ctl->halt = 1u;
+        ctl->halt_serial = serial;
+      }
+      return;
+    }
+  }
   for (int i = tid; i < kFineBins; i += blockDim.x) fh[i] = ctl->fhist[i];
   if (tid == 0) {
     s_bin = -1;
@@ -968,13 +980,13 @@ __global__ __launch_bounds__(1024) void select_decide(const Filter* filt_in, Fil
   const bool capped = (int64_t)nw > K;
   const uint64_t need = (uint64_t)(K - 1);
   uint64_t sel_lo = 0, sel_hi = 0, sel_need = 0;
-  bool none_kept = false;
+  bool none_kept = false, coarse = false;
   if (capped && need == 0) {
     none_kept = true;
   } else if (capped) {
     uint64_t win_lo = 0, win_hi = 0;
-    if (fin.cap_active) {
-      const double pred = __longlong_as_double((long long)fin.kth_bits) / fin.cI;
+    if (fin.ref_bits) {
+      const double pred = __longlong_as_double((long long)fin.ref_bits) / fin.cI;
       const uint64_t cb = abs_bits(pred);
       win_lo = cb > kFineHalf ? cb - kFineHalf : 0;
       win_hi = win_lo + 2 * kFineHalf;
@@ -993,16 +1005,9 @@ __global__ __launch_bounds__(1024) void select_decide(const Filter* filt_in, Fil
       if (tid == 0) s_bin = -1;
       __syncthreads();
     }
-    if (!fine_ok) {
-      find_from_top(h, kHistBins, 0, need, scr, &s_bin, &s_above);
-      const int b = s_bin < 0 ? 0 : s_bin;
-      sel_lo = b == 0 ? 0ull : ((uint64_t)(b + kHistBase) << kHistShift);
-      sel_hi = b == kHistBins - 1 ? ~0ull : ((uint64_t)(b + 1 + kHistBase) << kHistShift);
-      sel_need = need - (s_bin < 0 ? 0 : s_above);
-    }
+    coarse = !fine_ok;
   }
   __syncthreads();
-  for (int i = tid; i < kHistBins; i += blockDim.x) ctl->hist[i] = 0;
   for (int i = tid; i < kFineBins; i += blockDim.x) ctl->fhist[i] = 0;
   if (tid < kMaxClasses * kMaxClasses) {
     plan_next->cnt[tid / kMaxClasses][tid % kMaxClasses] = 0;
@@ -1021,14 +1026,21 @@ __global__ __launch_bounds__(1024) void select_decide(const Filter* filt_in, Fil
     f.kth_bits = none_kept ? 0x7fffffffffffffffull : 0ull;
     f.tie_active = 0;
     f.n_survivors = capped ? (uint64_t)K : nw;
+    // reference for the next gate's window: the exact K-th value once known
+    // (select_exact), else the previous reference carried into this scale
+    f.ref_bits = 0;
+    if (!capped && fin.ref_bits) f.ref_bits = abs_bits(__longlong_as_double((long long)fin.ref_bits) / fin.cI);
     *filt_out = f;
     ctl->term_updates += (double)fin.n_survivors;
     ctl->alg_elems += (double)fin.n_survivors + (double)f.n_survivors;
     ctl->gates += 1;
+    if (spec && fin.cap_active) ctl->spec_gates += 1;
     if (capped) ctl->cap_hit = 1;
     ctl->sel_lo = sel_lo;
     ctl->sel_hi = sel_hi;
     ctl->sel_need = (capped && !none_kept) ? (uint32_t)sel_need : 0u;
+    ctl->need_coarse = (capped && !none_kept && coarse) ? 1u : 0u;
+    if (ctl->need_coarse) ctl->sel_need = (uint32_t)need;  // resolved by select_coarse_pick
     ctl->cand_count = 0;
     ctl->ticket = 0;
     ctl->n_written_nonid = 0;
@@ -1037,11 +1049,83 @@ __global__ __launch_bounds__(1024) void select_decide(const Filter* filt_in, Fil
   }
 }
 
+// Clear what a gate accumulates, before a gate is redone after a failed
+// speculation (select_decide does this for the following gate otherwise).
+__global__ void prepare_kernel(Plan* plan_out, Ctl* ctl) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kHistBins; i += blockDim.x) ctl->hist[i] = 0;
+  for (int i = tid; i < kFineBins; i += blockDim.x) ctl->fhist[i] = 0;
+  if (tid < kMaxClasses * kMaxClasses) {
+    plan_out->cnt[tid / kMaxClasses][tid % kMaxClasses] = 0;
+    plan_out->ncnt[tid / kMaxClasses][tid % kMaxClasses] = 0;
+  }
+  if (tid == 0) {
+    ctl->ticket = 0;
+    ctl->n_written_nonid = 0;
+    ctl->n_above_hi = 0;
+    ctl->have_cI = 0;
+    ctl->cand_count = 0;
+    ctl->sel_need = 0;
+    ctl->need_coarse = 0;
+    ctl->halt = 0;
+  }
+}
+
+// Fallback when the K-th value is outside the fine window: full histogram of
+// the stored non-identity |c| values (16 bins per octave).
+template <int NW>
+__global__ __launch_bounds__(256) void select_coarse_hist(Side out, const Plan* plan, Ctl* ctl) {
+  __shared__ uint32_t h[kHistBins];
+  if (ctl->error || ctl->halt || !ctl->need_coarse) return;
+  for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  const Plan& p = *plan;
+  const int nc = 1 << p.wc, ne = 1 << p.we;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (int c = 0; c < nc; ++c)
+    for (int e = 0; e < ne; ++e) {
+      const uint64_t base = p.base[c][e];
+      const uint64_t cnt = p.cnt[c][e];
+      for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
+        if (c == 0 && e == 0 && i == 0) continue;  // the identity is the first string of region (0,0)
+        atomicAdd(&h[hist_bin(abs_bits(out.coef[base + i]))], 1u);
+      }
+    }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kHistBins; i += blockDim.x)
+    if (h[i]) atomicAdd(&ctl->hist[i], h[i]);
+}
+
+__global__ __launch_bounds__(1024) void select_coarse_pick(Ctl* ctl) {
+  __shared__ uint32_t h[kHistBins];
+  __shared__ uint64_t scr[1024];
+  __shared__ int s_bin;
+  __shared__ uint64_t s_above;
+  if (ctl->error || ctl->halt || !ctl->need_coarse) return;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kHistBins; i += blockDim.x) h[i] = ctl->hist[i];
+  if (tid == 0) {
+    s_bin = -1;
+    s_above = 0;
+  }
+  __syncthreads();
+  const uint64_t need = ctl->sel_need;
+  find_from_top(h, kHistBins, 0, need, scr, &s_bin, &s_above);
+  const int b = s_bin < 0 ? 0 : s_bin;
+  for (int i = tid; i < kHistBins; i += blockDim.x) ctl->hist[i] = 0;
+  if (tid == 0) {
+    ctl->sel_lo = b == 0 ? 0ull : ((uint64_t)(b + kHistBase) << kHistShift);
+    ctl->sel_hi = b == kHistBins - 1 ? ~0ull : ((uint64_t)(b + 1 + kHistBase) << kHistShift);
+    ctl->sel_need = (uint32_t)(need - (s_bin < 0 ? 0 : s_above));
+    ctl->need_coarse = 0;
+  }
+}
+
 // Collect the stored non-identity elements whose |c| bits lie in the
 // selected range.
 template <int NW>
 __global__ void select_collect(Side out, const Plan* plan, Ctl* ctl, SelBuf sel) {
-  if (ctl->error || ctl->sel_need == 0) return;
+  if (ctl->error || ctl->halt || ctl->sel_need == 0) return;
   const uint64_t lo = ctl->sel_lo, hi = ctl->sel_hi;
   const Plan& p = *plan;
   const int nc = 1 << p.wc, ne = 1 << p.we;
@@ -1078,7 +1162,7 @@ __global__ __launch_bounds__(1024) void select_exact(Side out, Filter* filt_out,
   __shared__ uint64_t s_above;
   __shared__ uint32_t s_cnt0;
   __shared__ unsigned long long s_ntie;
-  if (ctl->error || ctl->sel_need == 0) return;
+  if (ctl->error || ctl->halt || ctl->sel_need == 0) return;
   const int tid = threadIdx.x;
   const uint64_t m = ctl->cand_count < sel.cap ? ctl->cand_count : sel.cap;
   uint64_t prefix = 0, mask = 0, need = ctl->sel_need;
@@ -1112,6 +1196,7 @@ __global__ __launch_bounds__(1024) void select_exact(Side out, Filter* filt_out,
   const uint32_t need_eq = (uint32_t)need;
   if (tid == 0) {
     filt_out->kth_bits = kth;
+    filt_out->ref_bits = kth;
     filt_out->tie_active = 0;
     s_ntie = 0;
   }
@@ -1296,15 +1381,24 @@ hipError_t launch_gate(int nw, const GateParams& gp, Side in, Side out, const Pl
   return hipGetLastError();
 }
 
+hipError_t launch_prepare(Plan* plan_out, Ctl* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(1024), 0, st, plan_out, ctl);
+  return hipGetLastError();
+}
+
 hipError_t launch_select(int nw, Side out, const Plan* plan_out, const Filter* filt_in,
                          Filter* filt_out, Plan* plan_next, Ctl* ctl, SelBuf sel, const RepPos& rp,
-                         int64_t K, int cap_fail, int grid, hipStream_t st) {
+                         int64_t K, int cap_fail, int spec, uint64_t serial, int grid, hipStream_t st) {
   hipLaunchKernelGGL(select_decide, dim3(1), dim3(1024), 0, st, filt_in, filt_out, plan_next, ctl, K,
-                     cap_fail);
+                     cap_fail, spec, serial);
   if (nw == 2) {
+    hipLaunchKernelGGL(select_coarse_hist<2>, dim3(grid), dim3(256), 0, st, out, plan_out, ctl);
+    hipLaunchKernelGGL(select_coarse_pick, dim3(1), dim3(1024), 0, st, ctl);
     hipLaunchKernelGGL(select_collect<2>, dim3(grid), dim3(256), 0, st, out, plan_out, ctl, sel);
     hipLaunchKernelGGL(select_exact<2>, dim3(1), dim3(1024), 0, st, out, filt_out, ctl, sel, rp);
   } else {
+    hipLaunchKernelGGL(select_coarse_hist<4>, dim3(grid), dim3(256), 0, st, out, plan_out, ctl);
+    hipLaunchKernelGGL(select_coarse_pick, dim3(1), dim3(1024), 0, st, ctl);
     hipLaunchKernelGGL(select_collect<4>, dim3(grid), dim3(256), 0, st, out, plan_out, ctl, sel);
     hipLaunchKernelGGL(select_exact<4>, dim3(1), dim3(1024), 0, st, out, filt_out, ctl, sel, rp);
   }

@@ -224,3 +224,28 @@ def test_export_canonical_and_unique():
     assert len(set(keys)) == len(keys)
     assert keys[0] == (0, 0) and c[0] == 1.0
     e.close()
+
+
+@pytest.mark.parametrize("margin", [0.9, 1.0, 0.5])
+def test_speculation_never_changes_results(margin):
+    """The speculative write threshold is a pure speed device: a tight margin
+    (many redone gates) and speculation off give the same bits."""
+    w = W.config2(K=4096)
+    ref = None
+    for spec in (0, 1):
+        e = P.engine_for(w)
+        e.set_option("speculation", spec)
+        e.set_option("spec_margin", margin)
+        st = e.evolve(w.dtau, 3)
+        S = e.state()
+        if ref is None:
+            ref = S
+            assert st["spec_gates"] == 0
+        else:
+            assert S == ref
+            assert st["spec_gates"] > 0
+            if margin == 1.0:
+                assert st["spec_retries"] > 0
+        e.close()
+    o = c_oracle.run_workload(w, n_steps=3)
+    assert_same_state(o.state(), ref)
