@@ -82,6 +82,9 @@ struct itpp_ctx_s {
 namespace {
 
 const char* kVersion = "itpp gfx950 merge-join engine 0.2";
+// The look-back records carry 12-bit epoch tags that repeat every 4095
+// gates: clear them every 2048 gates.
+constexpr uint32_t kStatusClearEvery = 2048;
 // Host synchronisation period (gates) for the speculation check.
 constexpr int64_t kSyncEvery = 512;
 thread_local std::string g_create_error = "no error";
@@ -266,7 +269,7 @@ itpp_status itpp_create(const itpp_config* cfg, itpp_ctx* out) {
   const int tile = gate_tile(c->NW);
   c->status_cap = c->cap / (uint64_t)tile + 16;
   const uint64_t sel_cap = 2 * kmax + 64;
-  const uint64_t bytes = 2 * c->cap * elem_bytes + c->status_cap * sizeof(TileStatus) +
+  const uint64_t bytes = 2 * c->cap * elem_bytes + c->status_cap * kStatusWords * sizeof(TileStatus) +
                          sel_cap * (16 + 8 * (uint64_t)c->NW) + 4096;
   if (cfg->device_bytes_limit > 0 && bytes > (uint64_t)cfg->device_bytes_limit) {
     delete c;
@@ -280,7 +283,7 @@ itpp_status itpp_create(const itpp_config* cfg, itpp_ctx* out) {
   if (ok) ok = dalloc(c, &c->plan, 2) == hipSuccess;
   if (ok) ok = dalloc(c, &c->filt, 2) == hipSuccess;
   if (ok) ok = dalloc(c, &c->ctl, 1) == hipSuccess;
-  if (ok) ok = dalloc(c, &c->status, c->status_cap) == hipSuccess;
+  if (ok) ok = dalloc(c, &c->status, c->status_cap * kStatusWords) == hipSuccess;
   if (ok) ok = dalloc(c, &c->part, 2 * (c->status_cap + kMaxClasses + 4)) == hipSuccess;
   if (ok) ok = dalloc(c, &c->sel.cand_bits, sel_cap) == hipSuccess;
   if (ok) ok = dalloc(c, &c->sel.cand_idx, sel_cap) == hipSuccess;
@@ -293,7 +296,7 @@ itpp_status itpp_create(const itpp_config* cfg, itpp_ctx* out) {
     return create_fail(ITPP_ERR_OOM, "hipMalloc of the state buffers failed");
   }
   c->sel.cap = sel_cap;
-  he = hipMemsetAsync(c->status, 0, c->status_cap * sizeof(TileStatus), c->stream);
+  he = hipMemsetAsync(c->status, 0, c->status_cap * kStatusWords * sizeof(TileStatus), c->stream);
   if (he == hipSuccess) he = hipMemsetAsync(c->plan, 0, 2 * sizeof(Plan), c->stream);
   if (he != hipSuccess) {
     free_all(c);
@@ -459,6 +462,7 @@ static itpp_status enqueue_gate(itpp_ctx c, double dtau, bool spec) {
     gp.qm1[q >> 6] |= 1ull << (q & 63);
   }
   gp.tile = gate_tile(c->NW);
+  if (c->epoch % kStatusClearEvery == 0) HIP_TRY(c, launch_clear_status(c->status, c->status_cap, c->stream));
   gp.epoch = c->epoch;
   c->epoch = (c->epoch + 1) & 0x3fffffffu;
   if (c->epoch == 0) c->epoch = 1;
@@ -474,6 +478,7 @@ static itpp_status enqueue_gate(itpp_ctx c, double dtau, bool spec) {
   for (int b = 0; b < nbits; ++b) rp.pos[b] = (uint8_t)pos1[b];
   const int in = c->cur, out = c->cur ^ 1;
   const int pin = c->par, pout = c->par ^ 1;
+  HIP_TRY(c, launch_partition(c->NW, gp, c->side[in], c->plan + pin, c->ctl, c->part, c->stream));
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
   if (c->timing) {
     if (c->ev_used + 3 > 3 * 4096) HIP_TRY(c, drain_events(c));
@@ -483,7 +488,7 @@ static itpp_status enqueue_gate(itpp_ctx c, double dtau, bool spec) {
     HIP_TRY(c, hipEventRecord(e0, c->stream));
   }
   HIP_TRY(c, launch_gate(c->NW, gp, c->side[in], c->side[out], c->plan + pin, c->plan + pout, c->filt + pin,
-                         c->ctl, c->status, c->part, c->cus * 2, c->stream));
+                         c->ctl, c->status, c->part, c->cus * gate_wgs_per_cu(), c->stream));
   if (c->timing) HIP_TRY(c, hipEventRecord(e1, c->stream));
   HIP_TRY(c, launch_select(c->NW, c->side[out], c->plan + pout, c->filt + pin, c->filt + pout, c->plan + pin,
                            c->ctl, c->sel, rp, c->cfg.max_terms, c->cfg.cap_policy == ITPP_CAP_FAIL ? 1 : 0,

@@ -91,13 +91,16 @@ enum : uint32_t {
   kErrPhase = 5,       // commuting strings gave an imaginary phase
 };
 
-// Look-back record of one tile: words [0, 2C) hold the tile's aggregate
-// counts, words [2C, 4C) its inclusive prefix (C = kMaxClasses; two output
-// streams per tile).  Each word is (epoch << 32) | count, so a single atomic
-// load both validates and reads a counter.
-struct TileStatus {
-  unsigned long long w[4 * kMaxClasses];
-};
+// Look-back records, as dense word arrays of n = status_cap entries each (so
+// that 64 consecutive tiles are one coalesced load): word array s (s = 0, 1)
+// at [s*n, s*n + n) packs a tile's output counts of stream s (class cA / cB
+// of the join) for the 4 next classes as 12-bit fields (bits 0..47), a
+// 12-bit epoch tag (bits 52..63) and, in bit 48, a flag set once the
+// inclusive prefix is published; word array 2 + q holds the inclusive prefix
+// of counter q as (epoch << 32) | count.  Every word validates itself, so
+// single relaxed atomic loads suffice.
+constexpr int kStatusWords = 2 + 2 * kMaxClasses;
+typedef unsigned long long TileStatus;
 
 // Device arrays of one side of the ping-pong state buffers.
 struct Side {
@@ -154,6 +157,8 @@ struct SelBuf {
 
 // Host launchers (defined in itpp_kernels.hip).
 hipError_t launch_init(int nw, Side s0, Plan* plan, Filter* filt, Ctl* ctl, int w0, hipStream_t st);
+hipError_t launch_partition(int nw, const GateParams& gp, Side in, const Plan* plan_in, Ctl* ctl, uint64_t* part,
+                            hipStream_t st);
 hipError_t launch_gate(int nw, const GateParams& gp, Side in, Side out, const Plan* plan_in,
                        Plan* plan_out, const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part,
                        int grid, hipStream_t st);
@@ -161,6 +166,7 @@ hipError_t launch_select(int nw, Side out, const Plan* plan_out, const Filter* f
                          Filter* filt_out, Plan* plan_next, Ctl* ctl, SelBuf sel, const RepPos& rp,
                          int64_t K, int cap_fail, int spec, uint64_t serial, int grid, hipStream_t st);
 hipError_t launch_prepare(Plan* plan_out, Ctl* ctl, hipStream_t st);
+hipError_t launch_clear_status(TileStatus* status, uint64_t n, hipStream_t st);
 hipError_t launch_observe(int nw, Side s, const Plan* plan, const Filter* filt, const RepPos& rp,
                           const uint64_t* ox, const uint64_t* oz, const double* oc, int32_t m,
                           double* result, Ctl* ctl, hipStream_t st);
@@ -168,5 +174,6 @@ hipError_t launch_export(int nw, Side s, const Plan* plan, const Filter* filt, c
                          uint64_t* ex, uint64_t* ez, double* ec, unsigned long long* count,
                          uint64_t limit, int grid, hipStream_t st);
 int gate_tile(int nw);
+int gate_wgs_per_cu();
 
 }  // namespace itpp

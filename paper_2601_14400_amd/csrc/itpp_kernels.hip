@@ -413,6 +413,7 @@ __global__ __launch_bounds__(256) void partition_kernel(GateParams gp, Side in, 
 // region positions; (4) every element writes its outputs.
 template <int NW, int BLOCK, int TILE>
 struct GateSmem {
+  static_assert(TILE + 1 < 4096, "tile counts are packed in 12-bit look-back fields");
   static constexpr int CAPT = TILE + 2;
   static constexpr int PER = (CAPT + BLOCK - 1) / BLOCK;
   uint64_t key[NW][CAPT];
@@ -576,11 +577,12 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
     }
     __syncthreads();
 
-    // (2) merge walk over merged positions [m0, m0 + PER)
+    // (2) merge walk over merged positions [m0, m0 + PER): one element per
+    // step, A before B on equal keys; an equal B follows its A partner
     uint64_t c0 = 0, c1 = 0;  // run counts per next class (16-bit lanes): stream cA, stream cB
-    int xs[2 * (PER + 1)];    // elements handled by this thread, slot 2*step+side
+    int xs[PER];              // element handled at step s
 #pragma unroll
-    for (int q = 0; q < 2 * (PER + 1); ++q) xs[q] = -1;
+    for (int q = 0; q < PER; ++q) xs[q] = -1;
     {
       const int m0 = tid * PER;
       const int m1 = (m0 + PER < nt) ? m0 + PER : nt;
@@ -589,81 +591,78 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
         int hi = m0 < nAt ? m0 : nAt;
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
-          const Key<NW> a = lds_key<NW, TILE>(sm.key, mid);
-          const Key<NW> b = lds_key<NW, TILE>(sm.key, nAt + (m0 - mid - 1));
-          if (!key_less(b, a))
+          const Key<NW> ka = lds_key<NW, TILE>(sm.key, mid);
+          const Key<NW> kb = lds_key<NW, TILE>(sm.key, nAt + (m0 - mid - 1));
+          if (!key_less(kb, ka))
             lo = mid + 1;
           else
             hi = mid;
         }
         int a = lo, b = m0 - lo;
-        if (a > 0 && b < nBt) {
-          if (key_eq(lds_key<NW, TILE>(sm.key, a - 1), lds_key<NW, TILE>(sm.key, nAt + b))) ++b;
-        }
 #pragma unroll
-        for (int step = 0; step <= PER; ++step) {
+        for (int step = 0; step < PER; ++step) {
           if (a + b >= m1) break;
           const bool haveA = a < nAt, haveB = b < nBt;
           Key<NW> ka, kb;
           if (haveA) ka = lds_key<NW, TILE>(sm.key, a);
           if (haveB) kb = lds_key<NW, TILE>(sm.key, nAt + b);
-          const bool takeA = haveA && (!haveB || !key_less(kb, ka));
-          const bool eq = takeA && haveB && key_eq(ka, kb);
-          // elements handled in this step: A[a] (if takeA), B[b] (if !takeA or eq)
-#pragma unroll
-          for (int side = 0; side < 2; ++side) {
-            const bool isA = side == 0;
-            if (isA && !takeA) continue;
-            if (!isA && takeA && !eq) continue;
-            const int x = isA ? a : nAt + b;
-            const int y = isA ? nAt + b : a;  // partner slot if eq
-            uint16_t inf = sm.info[x];
-            const bool sv = inf & 1, comm = (inf >> 1) & 1;
-            uint16_t rsx = 0, rbx = 0;
-            if (sv) {
-              const bool paired = eq && (sm.info[y] & 1);
-              const double c = sm.coef[x];
-              const double cp = paired ? sm.coef[y] : 0.0;
-              const Key<NW> k = isA ? ka : kb;
-              const Key<NW> ownk = isA ? k : xor_top(k, nbits, w);
-              bool neg = false;
-              if (comm) {
-                const int e4 = phase_negative(ownk, gp);
-                if (e4 & 1) atomicMax(&ctl->error, kErrPhase);
-                neg = (e4 == 2);
-                if (neg) inf |= 512u;
-              }
-              double vs, vb;
-              values_from(c, comm, paired, cp, neg, gp, vs, vb);
-              const bool hs = fabs(vs) > tw;
-              const bool hb = comm && !paired && fabs(vb) > tw;
-              if (paired) {
-                inf |= 4u;
-                sm.partner[x] = (uint16_t)y;
-              }
-              int es = 0;
-              for (int mm = 0; mm < gp.w1; ++mm) es |= get_bit(ownk, gp.epos[mm]) << mm;
-              if (hs) {
-                inf |= (uint16_t)(8u | (es << 4));
-                uint64_t& cc = isA ? c0 : c1;
-                rsx = (uint16_t)lane16(cc, es);
-                cc += 1ull << (16 * es);
-              }
-              if (hb) {
-                const int eb = es ^ gp.ov;  // the branch differs in this gate's bits only
-                inf |= (uint16_t)(64u | (eb << 7));
-                uint64_t& cc = isA ? c1 : c0;
-                rbx = (uint16_t)lane16(cc, eb);
-                cc += 1ull << (16 * eb);
-              }
-            }
-            sm.info[x] = inf;
-            sm.rs[x] = rsx;
-            sm.rb[x] = rbx;
-            xs[2 * step + side] = x;
+          const bool isA = haveA && (!haveB || !key_less(kb, ka));
+          const int x = isA ? a : nAt + b;
+          // partner: for A the current B if equal, for B the previous A if equal
+          int y = -1;
+          if (isA) {
+            if (haveB && key_eq(ka, kb)) y = nAt + b;
+          } else if (a > 0) {
+            if (key_eq(lds_key<NW, TILE>(sm.key, a - 1), kb)) y = a - 1;
           }
-          if (takeA) ++a;
-          if (!takeA || eq) ++b;
+          const Key<NW> k = isA ? ka : kb;
+          uint16_t inf = sm.info[x];
+          const bool sv = inf & 1, comm = (inf >> 1) & 1;
+          uint16_t rsx = 0, rbx = 0;
+          if (sv) {
+            const bool paired = (y >= 0) && (sm.info[y] & 1);
+            const double c = sm.coef[x];
+            const double cp = paired ? sm.coef[y] : 0.0;
+            const Key<NW> ownk = isA ? k : xor_top(k, nbits, w);
+            bool neg = false;
+            if (comm) {
+              const int e4 = phase_negative(ownk, gp);
+              if (e4 & 1) atomicMax(&ctl->error, kErrPhase);
+              neg = (e4 == 2);
+              if (neg) inf |= 512u;
+            }
+            double vs, vb;
+            values_from(c, comm, paired, cp, neg, gp, vs, vb);
+            const bool hs = fabs(vs) > tw;
+            const bool hb = comm && !paired && fabs(vb) > tw;
+            if (paired) {
+              inf |= 4u;
+              sm.partner[x] = (uint16_t)y;
+            }
+            int es = 0;
+            for (int mm = 0; mm < gp.w1; ++mm) es |= get_bit(ownk, gp.epos[mm]) << mm;
+            // A: self -> stream cA, branch -> stream cB; B: the reverse
+            uint64_t sinc = 0, binc = 0;
+            if (hs) {
+              inf |= (uint16_t)(8u | (es << 4));
+              sinc = 1ull << (16 * es);
+              rsx = (uint16_t)lane16(isA ? c0 : c1, es);
+            }
+            if (hb) {
+              const int eb = es ^ gp.ov;  // the branch differs in this gate's bits only
+              inf |= (uint16_t)(64u | (eb << 7));
+              binc = 1ull << (16 * eb);
+              rbx = (uint16_t)lane16(isA ? c1 : c0, eb);
+            }
+            c0 += isA ? sinc : binc;
+            c1 += isA ? binc : sinc;
+          }
+          sm.info[x] = inf;
+          sm.rs[x] = rsx;
+          sm.rb[x] = rbx;
+          xs[step] = x;
+          if (isA) ++a;
+          else ++b;
         }
       }
     }
@@ -673,7 +672,7 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
       uint64_t p0 = c0, p1 = c1;
       block_scan2<BLOCK>(p0, p1, sm.wa, sm.wb, t0, t1);
 #pragma unroll
-      for (int q = 0; q < 2 * (PER + 1); ++q) {
+      for (int q = 0; q < PER; ++q) {
         const int x = xs[q];
         if (x < 0) continue;
         const uint16_t inf = sm.info[x];
@@ -696,8 +695,18 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
         agg[kMaxClasses + e] = lane16(sm.tot1, e);
       }
       constexpr int NQ = 2 * kMaxClasses;
-      TileStatus* st = status + t;
-      const unsigned long long tag = (unsigned long long)gp.epoch << 32;
+      const uint64_t SN = gp.status_cap;
+      const unsigned long long tag32 = (unsigned long long)gp.epoch << 32;
+      const unsigned long long tag12 = (unsigned long long)(gp.epoch % 4095u + 1u) << 52;
+      const unsigned long long kInclReady = 1ull << 48;
+      unsigned long long aw[2];
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        unsigned long long v = tag12;
+#pragma unroll
+        for (int e = 0; e < kMaxClasses; ++e) v |= (unsigned long long)agg[sd * kMaxClasses + e] << (12 * e);
+        aw[sd] = v;
+      }
       uint32_t excl[NQ];
 #pragma unroll
       for (int q = 0; q < NQ; ++q) excl[q] = 0;
@@ -705,83 +714,117 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
         if (lane == 0) {
 #pragma unroll
           for (int q = 0; q < NQ; ++q)
-            __hip_atomic_store(&st->w[NQ + q], tag | agg[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&status[(2 + q) * SN + t], tag32 | agg[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+          for (int sd = 0; sd < 2; ++sd)
+            __hip_atomic_store(&status[sd * SN + t], aw[sd] | kInclReady, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       } else {
         if (lane == 0) {
 #pragma unroll
-          for (int q = 0; q < NQ; ++q)
-            __hip_atomic_store(&st->w[q], tag | agg[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          for (int sd = 0; sd < 2; ++sd)
+            __hip_atomic_store(&status[sd * SN + t], aw[sd], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         // each lane inspects LB consecutive predecessors per round (window 64 * LB)
-        constexpr int LB = 2;
+        constexpr int LB = 8;
         const int64_t first = (int64_t)sm.L.tiles_before[j];
         int64_t khi = (int64_t)t - 1;
         bool done = false;
         while (!done) {
-          uint32_t val[LB][NQ];
-          int kind[LB];  // 0 aggregate, 1 inclusive (or before the join: zero)
+          unsigned long long w0[LB], w1[LB];
+          // position r*64 + lane is predecessor khi - (r*64 + lane): one
+          // coalesced load of 64 consecutive tiles per r
 #pragma unroll
           for (int r = 0; r < LB; ++r) {
-            const int64_t k = khi - (int64_t)(lane * LB + r);
-            kind[r] = 1;
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) val[r][q] = 0;
+            const int64_t k = khi - (int64_t)(r * 64 + lane);
+            w0[r] = kInclReady;  // before the join's first tile: never needed, reads as ready with zero
+            w1[r] = 0;
             if (k < first) continue;
             uint32_t spins = 0;
             for (;;) {
-              unsigned long long wv[2 * NQ];
-#pragma unroll
-              for (int q = 0; q < 2 * NQ; ++q)
-                wv[q] = __hip_atomic_load(&status[k].w[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              bool av = true, iv = true;
-#pragma unroll
-              for (int q = 0; q < NQ; ++q) {
-                av = av && ((wv[q] >> 32) == gp.epoch);
-                iv = iv && ((wv[NQ + q] >> 32) == gp.epoch);
-              }
-              if (iv || av) {
-                kind[r] = iv ? 1 : 0;
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) val[r][q] = (uint32_t)(iv ? wv[NQ + q] : wv[q]);
+              const unsigned long long a0 = __hip_atomic_load(&status[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              const unsigned long long a1 = __hip_atomic_load(&status[SN + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              if ((a0 >> 52) == (tag12 >> 52) && (a1 >> 52) == (tag12 >> 52)) {
+                w0[r] = a0;
+                w1[r] = a1;
                 break;
               }
               if (++spins > (1u << 22)) {
                 atomicMax(&ctl->error, kErrSpin);
+                w0[r] = kInclReady;
                 break;
               }
               __builtin_amdgcn_s_sleep(1);
             }
           }
-          // nearest inclusive predecessor: lowest (lane, r) position with kind 1
-          int pos_incl = 64 * LB;
+          // nearest predecessor whose inclusive prefix is published
+          uint32_t best = 64 * LB;
 #pragma unroll
           for (int r = LB - 1; r >= 0; --r)
-            if (kind[r]) pos_incl = lane * LB + r;
-          uint32_t best = (uint32_t)pos_incl;
+            if (w0[r] & kInclReady) best = (uint32_t)(r * 64 + lane);
 #pragma unroll
           for (int d = 32; d >= 1; d >>= 1) {
             const uint32_t o = __shfl_xor(best, d, 64);
             best = o < best ? o : best;
           }
+          // aggregates of the predecessors nearer than that one
+          uint32_t sum[NQ];
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) sum[q] = 0;
+#pragma unroll
+          for (int r = 0; r < LB; ++r) {
+            if ((uint32_t)(r * 64 + lane) < best) {
+#pragma unroll
+              for (int e = 0; e < kMaxClasses; ++e) {
+                sum[e] += (uint32_t)((w0[r] >> (12 * e)) & 0xfffull);
+                sum[kMaxClasses + e] += (uint32_t)((w1[r] >> (12 * e)) & 0xfffull);
+              }
+            }
+          }
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
-            uint32_t v = 0;
-#pragma unroll
-            for (int r = 0; r < LB; ++r)
-              if ((uint32_t)(lane * LB + r) <= best) v += val[r][q];
+            uint32_t v = sum[q];
 #pragma unroll
             for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
             excl[q] += v;
           }
           done = best < (uint32_t)(64 * LB);
+          if (done) {
+            const int64_t kp = khi - (int64_t)best;
+            if (kp >= first) {
+              // inclusive prefix of that predecessor (lane q reads counter q)
+              uint32_t iv = 0;
+              if (lane < NQ) {
+                uint32_t spins = 0;
+                for (;;) {
+                  const unsigned long long x =
+                      __hip_atomic_load(&status[(2 + lane) * SN + kp], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                  if ((x >> 32) == gp.epoch) {
+                    iv = (uint32_t)x;
+                    break;
+                  }
+                  if (++spins > (1u << 22)) {
+                    atomicMax(&ctl->error, kErrSpin);
+                    break;
+                  }
+                  __builtin_amdgcn_s_sleep(1);
+                }
+              }
+#pragma unroll
+              for (int q = 0; q < NQ; ++q) excl[q] += __shfl(iv, q, 64);
+            }
+          }
           khi -= 64 * LB;
         }
         if (lane == 0) {
 #pragma unroll
           for (int q = 0; q < NQ; ++q)
-            __hip_atomic_store(&st->w[NQ + q], tag | (excl[q] + agg[q]), __ATOMIC_RELAXED,
+            __hip_atomic_store(&status[(2 + q) * SN + t], tag32 | (excl[q] + agg[q]), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
+          __atomic_thread_fence(__ATOMIC_RELEASE);
+#pragma unroll
+          for (int sd = 0; sd < 2; ++sd)
+            __hip_atomic_store(&status[sd * SN + t], aw[sd] | kInclReady, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
       if (lane == 0) {
@@ -1047,6 +1090,18 @@ __global__ __launch_bounds__(1024) void select_decide(const Filter* filt_in, Fil
     ctl->n_above_hi = 0;
     ctl->have_cI = 0;
   }
+}
+
+// Reset the look-back records (their 12-bit epoch tags repeat every 4095
+// gates; the host clears them more often than that).
+__global__ void clear_status_kernel(TileStatus* status, uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * n; i += stride) status[i] = 0;
+}
+
+hipError_t launch_clear_status(TileStatus* status, uint64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(clear_status_kernel, dim3(256), dim3(256), 0, st, status, n);
+  return hipGetLastError();
 }
 
 // Clear what a gate accumulates, before a gate is redone after a failed
@@ -1341,19 +1396,31 @@ __global__ void export_kernel(Side s, const Plan* plan, const Filter* filt, RepP
 
 // ---------------------------------------------------------------------------
 // Host launchers.
-constexpr int kBlock = 512;
+#ifndef ITPP_GATE_BLOCK
+#define ITPP_GATE_BLOCK 1024
+#endif
+#ifndef ITPP_TILE_W1
+#define ITPP_TILE_W1 4000
+#endif
+#ifndef ITPP_TILE_W2
+#define ITPP_TILE_W2 2000
+#endif
+// Gate kernel shape: threads per workgroup and merged elements per tile
+// (one- and two-word keys); occupancy is 2048 / kBlock workgroups per CU.
+constexpr int kBlock = ITPP_GATE_BLOCK;
 template <int NW>
 struct TileFor;
 template <>
 struct TileFor<2> {
-  static constexpr int value = 2048;
+  static constexpr int value = ITPP_TILE_W1;
 };
 template <>
 struct TileFor<4> {
-  static constexpr int value = 1024;
+  static constexpr int value = ITPP_TILE_W2;
 };
 
 int gate_tile(int nw) { return nw == 2 ? TileFor<2>::value : TileFor<4>::value; }
+int gate_wgs_per_cu() { return 1024 / kBlock; }
 
 hipError_t launch_init(int nw, Side s0, Plan* plan, Filter* filt, Ctl* ctl, int w0, hipStream_t st) {
   if (nw == 2)
@@ -1363,21 +1430,27 @@ hipError_t launch_init(int nw, Side s0, Plan* plan, Filter* filt, Ctl* ctl, int 
   return hipGetLastError();
 }
 
-hipError_t launch_gate(int nw, const GateParams& gp, Side in, Side out, const Plan* plan_in,
-                       Plan* plan_out, const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part,
-                       int grid, hipStream_t st) {
+hipError_t launch_partition(int nw, const GateParams& gp, Side in, const Plan* plan_in, Ctl* ctl, uint64_t* part,
+                            hipStream_t st) {
   // one wavefront per tile boundary, four per block
   const uint64_t nb = gp.status_cap + kMaxClasses;
   const int pgrid = (int)((nb + 3) / 4);
-  if (nw == 2) {
+  if (nw == 2)
     hipLaunchKernelGGL(partition_kernel<2>, dim3(pgrid), dim3(256), 0, st, gp, in, plan_in, part, ctl);
-    hipLaunchKernelGGL((gate_kernel<2, kBlock, TileFor<2>::value>), dim3(grid), dim3(kBlock), 0, st, gp,
-                       in, out, plan_in, plan_out, filt_in, (const uint64_t*)part, ctl, status);
-  } else {
+  else
     hipLaunchKernelGGL(partition_kernel<4>, dim3(pgrid), dim3(256), 0, st, gp, in, plan_in, part, ctl);
-    hipLaunchKernelGGL((gate_kernel<4, kBlock, TileFor<4>::value>), dim3(grid), dim3(kBlock), 0, st, gp,
-                       in, out, plan_in, plan_out, filt_in, (const uint64_t*)part, ctl, status);
-  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gate(int nw, const GateParams& gp, Side in, Side out, const Plan* plan_in,
+                       Plan* plan_out, const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part,
+                       int grid, hipStream_t st) {
+  if (nw == 2)
+    hipLaunchKernelGGL((gate_kernel<2, kBlock, TileFor<2>::value>), dim3(grid), dim3(kBlock), 0, st, gp, in, out,
+                       plan_in, plan_out, filt_in, (const uint64_t*)part, ctl, status);
+  else
+    hipLaunchKernelGGL((gate_kernel<4, kBlock, TileFor<4>::value>), dim3(grid), dim3(kBlock), 0, st, gp, in, out,
+                       plan_in, plan_out, filt_in, (const uint64_t*)part, ctl, status);
   return hipGetLastError();
 }
 
