@@ -18,6 +18,11 @@
 //     (normalisation after every elementary gate, Sec. II.C).
 // cosh/sinh come from the C library once per gate, so results agree bit for
 // bit with the Python oracle.
+//
+// Single-precision form: coefficients are binary32, ch and sh are the double
+// values rounded to binary32, products and sums are binary32, the threshold
+// compares the widened magnitude with the double delta, normalisation divides
+// in double and rounds to binary32 (the same reading as the Python oracle).
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -66,33 +71,38 @@ bool canonical_less(const std::string& p, const std::string& q) {
 
 struct Oracle {
   int n = 0;
-  std::unordered_map<std::string, double> S;
+  int f32 = 0;
+  std::unordered_map<std::string, double> S;   // FP64 form
+  std::unordered_map<std::string, float> S32;  // FP32 form
   std::string err;
   double term_updates = 0.0;
   long long gates = 0;
 };
 
-}  // namespace
-
-extern "C" {
-
-void* itpp_oracle_new(int n) {
-  Oracle* o = new Oracle;
-  o->n = n;
-  o->S.emplace(std::string(n, 'I'), 1.0);
-  return o;
+template <typename T>
+std::unordered_map<std::string, T>& state(Oracle* o);
+template <>
+std::unordered_map<std::string, double>& state<double>(Oracle* o) {
+  return o->S;
+}
+template <>
+std::unordered_map<std::string, float>& state<float>(Oracle* o) {
+  return o->S32;
 }
 
-void itpp_oracle_free(void* h) { delete static_cast<Oracle*>(h); }
+template <typename T>
+int evolve_impl(Oracle* o, int n_terms, const char* strings, const double* alpha, int n_gates,
+                const int* term_idx, const double* mult, double dtau, long long n_steps, double delta,
+                long long K);
 
-const char* itpp_oracle_error(void* h) { return static_cast<Oracle*>(h)->err.c_str(); }
+}  // namespace
 
-// strings: n_terms * n characters, row-major.
-// Returns 0 on success, 1 if the identity coefficient is lost or not positive.
-int itpp_oracle_evolve(void* h, int n_terms, const char* strings, const double* alpha,
-                       int n_gates, const int* term_idx, const double* mult, double dtau,
-                       long long n_steps, double delta, long long K) {
-  Oracle* o = static_cast<Oracle*>(h);
+namespace {
+template <typename T>
+int evolve_impl(Oracle* o, int n_terms, const char* strings, const double* alpha, int n_gates,
+                const int* term_idx, const double* mult, double dtau, long long n_steps, double delta,
+                long long K) {
+  auto& S = state<T>(o);
   const int n = o->n;
   const std::string ident(n, 'I');
   std::vector<std::string> terms(n_terms);
@@ -102,18 +112,18 @@ int itpp_oracle_evolve(void* h, int n_terms, const char* strings, const double* 
       const std::string& Q = terms[term_idx[g]];
       if (Q == ident) continue;
       const double theta = alpha[term_idx[g]] * mult[g] * dtau;
-      const double ch = std::cosh(theta);
-      const double sh = std::sinh(theta);
+      const T ch = (T)std::cosh(theta);
+      const T sh = (T)std::sinh(theta);
       std::vector<int> sup;
       for (int j = 0; j < n; ++j)
         if (Q[j] != 'I') sup.push_back(j);
-      o->term_updates += (double)o->S.size();
+      o->term_updates += (double)S.size();
       // propagate and accumulate
-      std::unordered_map<std::string, double> out;
-      out.reserve(o->S.size() * 2 + 16);
-      for (const auto& kv : o->S) {
+      std::unordered_map<std::string, T> out;
+      out.reserve(S.size() * 2 + 16);
+      for (const auto& kv : S) {
         const std::string& P = kv.first;
-        const double c = kv.second;
+        const T c = kv.second;
         int anti = 0;
         for (int j : sup) {
           char a = P[j], b = Q[j];
@@ -135,20 +145,20 @@ int itpp_oracle_evolve(void* h, int n_terms, const char* strings, const double* 
           o->err = "commuting strings gave an imaginary phase";
           return 2;
         }
-        const double sign = (k == 0) ? 1.0 : -1.0;
-        out[P] += ch * c;
-        out[R] += -sh * sign * c;
+        const T sign = (k == 0) ? (T)1 : (T)-1;
+        out[P] += (T)(ch * c);
+        out[R] += (T)((T)(-sh * sign) * c);
       }
       // truncate: threshold
-      std::vector<std::pair<std::string, double>> kept;
+      std::vector<std::pair<std::string, T>> kept;
       kept.reserve(out.size());
       for (auto& kv : out)
-        if (std::fabs(kv.second) > delta) kept.emplace_back(kv.first, kv.second);
+        if ((double)std::fabs(kv.second) > delta) kept.emplace_back(kv.first, kv.second);
       // truncate: cap
       if ((long long)kept.size() > K) {
-        double cI = 0.0;
+        T cI = 0;
         bool have = false;
-        std::vector<std::pair<std::string, double>> others;
+        std::vector<std::pair<std::string, T>> others;
         others.reserve(kept.size());
         for (auto& kv : kept) {
           if (kv.first == ident) {
@@ -162,9 +172,8 @@ int itpp_oracle_evolve(void* h, int n_terms, const char* strings, const double* 
           o->err = "identity coefficient was truncated";
           return 1;
         }
-        auto better = [](const std::pair<std::string, double>& a,
-                         const std::pair<std::string, double>& b) {
-          double fa = std::fabs(a.second), fb = std::fabs(b.second);
+        auto better = [](const std::pair<std::string, T>& a, const std::pair<std::string, T>& b) {
+          T fa = std::fabs(a.second), fb = std::fabs(b.second);
           if (fa != fb) return fa > fb;
           return canonical_less(a.first, b.first);
         };
@@ -177,41 +186,80 @@ int itpp_oracle_evolve(void* h, int n_terms, const char* strings, const double* 
         kept.emplace_back(ident, cI);
         for (auto& kv : others) kept.push_back(kv);
       }
-      // normalise
+      // normalise (division in double)
       double cI = 0.0;
       bool have = false;
       for (auto& kv : kept)
         if (kv.first == ident) {
-          cI = kv.second;
+          cI = (double)kv.second;
           have = true;
         }
       if (!have || !(cI > 0.0) || !std::isfinite(cI)) {
         o->err = "bad identity coefficient";
         return 1;
       }
-      o->S.clear();
-      o->S.reserve(kept.size() * 2);
-      for (auto& kv : kept) o->S.emplace(kv.first, kv.second / cI);
+      S.clear();
+      S.reserve(kept.size() * 2);
+      for (auto& kv : kept) S.emplace(kv.first, (T)((double)kv.second / cI));
       ++o->gates;
     }
   }
   return 0;
 }
 
-long long itpp_oracle_size(void* h) { return (long long)static_cast<Oracle*>(h)->S.size(); }
+}  // namespace
+
+extern "C" {
+
+void* itpp_oracle_new(int n) {
+  Oracle* o = new Oracle;
+  o->n = n;
+  o->S.emplace(std::string(n, 'I'), 1.0);
+  return o;
+}
+
+void* itpp_oracle_new32(int n) {
+  Oracle* o = new Oracle;
+  o->n = n;
+  o->f32 = 1;
+  o->S32.emplace(std::string(n, 'I'), 1.0f);
+  return o;
+}
+
+void itpp_oracle_free(void* h) { delete static_cast<Oracle*>(h); }
+
+const char* itpp_oracle_error(void* h) { return static_cast<Oracle*>(h)->err.c_str(); }
+
+// strings: n_terms * n characters, row-major.
+// Returns 0 on success, 1 if the identity coefficient is lost or not positive.
+int itpp_oracle_evolve(void* h, int n_terms, const char* strings, const double* alpha,
+                       int n_gates, const int* term_idx, const double* mult, double dtau,
+                       long long n_steps, double delta, long long K) {
+  Oracle* o = static_cast<Oracle*>(h);
+  if (o->f32)
+    return evolve_impl<float>(o, n_terms, strings, alpha, n_gates, term_idx, mult, dtau, n_steps, delta, K);
+  return evolve_impl<double>(o, n_terms, strings, alpha, n_gates, term_idx, mult, dtau, n_steps, delta, K);
+}
+
+long long itpp_oracle_size(void* h) {
+  Oracle* o = static_cast<Oracle*>(h);
+  return (long long)(o->f32 ? o->S32.size() : o->S.size());
+}
 
 double itpp_oracle_term_updates(void* h) { return static_cast<Oracle*>(h)->term_updates; }
 
 // Writes the state in ascending (X, Z) order: strings (size*n chars) and coefs.
 void itpp_oracle_export(void* h, char* strings_out, double* coef_out) {
   Oracle* o = static_cast<Oracle*>(h);
-  std::vector<const std::pair<const std::string, double>*> v;
-  v.reserve(o->S.size());
-  for (const auto& kv : o->S) v.push_back(&kv);
-  std::sort(v.begin(), v.end(), [](auto* a, auto* b) { return canonical_less(a->first, b->first); });
+  std::vector<std::pair<std::string, double>> v;
+  if (o->f32)
+    for (const auto& kv : o->S32) v.emplace_back(kv.first, (double)kv.second);
+  else
+    for (const auto& kv : o->S) v.emplace_back(kv.first, kv.second);
+  std::sort(v.begin(), v.end(), [](const auto& a, const auto& b) { return canonical_less(a.first, b.first); });
   for (size_t i = 0; i < v.size(); ++i) {
-    std::memcpy(strings_out + i * o->n, v[i]->first.data(), o->n);
-    coef_out[i] = v[i]->second;
+    std::memcpy(strings_out + i * o->n, v[i].first.data(), o->n);
+    coef_out[i] = v[i].second;
   }
 }
 
@@ -219,7 +267,14 @@ void itpp_oracle_export(void* h, char* strings_out, double* coef_out) {
 void itpp_oracle_import(void* h, long long count, const char* strings, const double* coef) {
   Oracle* o = static_cast<Oracle*>(h);
   o->S.clear();
-  for (long long i = 0; i < count; ++i) o->S[std::string(strings + i * o->n, o->n)] = coef[i];
+  o->S32.clear();
+  for (long long i = 0; i < count; ++i) {
+    std::string k(strings + i * o->n, o->n);
+    if (o->f32)
+      o->S32[k] = (float)coef[i];
+    else
+      o->S[k] = coef[i];
+  }
 }
 
 }  // extern "C"

@@ -33,6 +33,8 @@ def _load():
         lib = ctypes.CDLL(LIB)
         lib.itpp_oracle_new.restype = ctypes.c_void_p
         lib.itpp_oracle_new.argtypes = [ctypes.c_int]
+        lib.itpp_oracle_new32.restype = ctypes.c_void_p
+        lib.itpp_oracle_new32.argtypes = [ctypes.c_int]
         lib.itpp_oracle_free.argtypes = [ctypes.c_void_p]
         lib.itpp_oracle_error.restype = ctypes.c_char_p
         lib.itpp_oracle_error.argtypes = [ctypes.c_void_p]
@@ -53,10 +55,10 @@ def _load():
 
 
 class COracle:
-    def __init__(self, n: int):
+    def __init__(self, n: int, precision: str = "f64"):
         self.n = n
         self._lib = _load()
-        self._h = self._lib.itpp_oracle_new(n)
+        self._h = self._lib.itpp_oracle_new32(n) if precision == "f32" else self._lib.itpp_oracle_new(n)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -103,8 +105,8 @@ class COracle:
         self._lib.itpp_oracle_import(self._h, len(keys), buf, coef.ctypes.data)
 
 
-def run_workload(w, n_steps=None, K=None) -> COracle:
-    o = COracle(w.n)
+def run_workload(w, n_steps=None, K=None, precision=None) -> COracle:
+    o = COracle(w.n, precision or w.precision)
     o.evolve(w.strings, w.alphas, w.schedule, w.dtau, w.n_steps if n_steps is None else n_steps,
              w.delta, w.K if K is None else K)
     return o

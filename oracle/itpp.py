@@ -35,11 +35,20 @@ Readings fixed here where the paper leaves a choice open:
 * ``cosh`` and ``sinh`` are evaluated once per gate with the C library
   (Python's ``math``), and each new coefficient is ``ch*c`` (or ``c`` for an
   anticommuting string) plus at most one branch term ``-sh*sign*c'``.
+
+Single-precision form (``precision="f32"``): coefficients are stored and
+propagated as IEEE binary32; ``ch`` and ``sh`` are the double values rounded
+to binary32; every product and sum of Eq. (ITPP_PropRules) is rounded to
+binary32; the threshold compares the binary32 magnitude (exactly widened) with
+the double ``delta``; normalisation divides in double and rounds the quotient
+to binary32; observables sum in double.
 """
 from __future__ import annotations
 
 import math
 from typing import Callable, Dict, Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
 
 # Single-qubit products a*b = i^k * r as (k mod 4, r): Pauli algebra.
 _MUL: Dict[Tuple[str, str], Tuple[int, str]] = {}
@@ -115,10 +124,29 @@ def apply_gate(S: Dict[str, float], Q: str, ch: float, sh: float) -> Dict[str, f
     return out
 
 
+def apply_gate_f32(S: Dict[str, np.float32], Q: str, ch: float, sh: float) -> Dict[str, np.float32]:
+    """Single-precision twin of ``apply_gate`` (binary32 products and sums)."""
+    ch32 = np.float32(ch)
+    sh32 = np.float32(sh)
+    out: Dict[str, np.float32] = {}
+    for P, c in S.items():
+        if not commutes(P, Q):
+            contribs = [(P, c)]
+        else:
+            k, R = pauli_product(Q, P)
+            if k % 2:
+                raise OracleError("commuting strings gave an imaginary phase")
+            t = np.float32(sh32 * c)
+            contribs = [(P, np.float32(ch32 * c)), (R, -t if k == 0 else t)]
+        for R, v in contribs:
+            out[R] = np.float32(out[R] + v) if R in out else np.float32(v)
+    return out
+
+
 def truncate(S: Dict[str, float], delta: float, K: int) -> Dict[str, float]:
     """Keep ``|c| > delta``; if more than ``K`` remain keep the identity and
     the ``K-1`` other strings of largest ``|c|`` (ties: smaller (X, Z))."""
-    kept = {P: c for P, c in S.items() if abs(c) > delta}
+    kept = {P: c for P, c in S.items() if abs(float(c)) > delta}
     if len(kept) <= K:
         return kept
     n = len(next(iter(kept)))
@@ -126,7 +154,7 @@ def truncate(S: Dict[str, float], delta: float, K: int) -> Dict[str, float]:
     if ident not in kept:
         raise OracleError("identity coefficient was truncated")
     others = [(P, c) for P, c in kept.items() if P != ident]
-    others.sort(key=lambda t: (-abs(t[1]), canonical_key(t[0])))
+    others.sort(key=lambda t: (-abs(float(t[1])), canonical_key(t[0])))
     out = {ident: kept[ident]}
     for P, c in others[: K - 1]:
         out[P] = c
@@ -141,6 +169,15 @@ def normalize(S: Dict[str, float], n: int) -> Tuple[Dict[str, float], float]:
     return {P: c / cI for P, c in S.items()}, cI
 
 
+def normalize_f32(S: Dict[str, np.float32], n: int) -> Tuple[Dict[str, np.float32], float]:
+    """Divide in double by the identity coefficient, round to binary32."""
+    cI = S.get(identity(n))
+    if cI is None or not math.isfinite(float(cI)) or float(cI) <= 0.0:
+        raise OracleError(f"bad identity coefficient {cI!r}")
+    d = float(cI)
+    return {P: np.float32(float(c) / d) for P, c in S.items()}, d
+
+
 def gate_angle(alpha: float, mult: float, dtau: float) -> float:
     return alpha * mult * dtau
 
@@ -148,14 +185,17 @@ def gate_angle(alpha: float, mult: float, dtau: float) -> float:
 def evolve(n: int, strings: Sequence[str], alphas: Sequence[float],
            schedule: Sequence[Tuple[int, float]], dtau: float, n_steps: int,
            delta: float, K: int, S0: Optional[Dict[str, float]] = None,
-           on_gate: Optional[Callable[[int, Dict[str, float], float], None]] = None
-           ) -> Tuple[Dict[str, float], Dict[str, float]]:
+           on_gate: Optional[Callable[[int, Dict[str, float], float], None]] = None,
+           precision: str = "f64") -> Tuple[Dict[str, float], Dict[str, float]]:
     """Algorithm 1 with per-gate truncation and normalisation.
 
     Returns ``(S, stats)`` with ``stats['term_updates']`` = sum over gates of
     the number of strings entering the gate.
     """
-    S = dict(S0) if S0 is not None else {identity(n): 1.0}
+    f32 = precision == "f32"
+    S = dict(S0) if S0 is not None else {identity(n): (np.float32(1.0) if f32 else 1.0)}
+    if f32:
+        S = {P: np.float32(c) for P, c in S.items()}
     ident = identity(n)
     updates = 0
     g = 0
@@ -170,9 +210,14 @@ def evolve(n: int, strings: Sequence[str], alphas: Sequence[float],
             ch = math.cosh(theta)
             sh = math.sinh(theta)
             updates += len(S)
-            Sp = apply_gate(S, Q, ch, sh)
-            St = truncate(Sp, delta, K)
-            S, cI = normalize(St, n)
+            if f32:
+                Sp = apply_gate_f32(S, Q, ch, sh)
+                St = truncate(Sp, delta, K)
+                S, cI = normalize_f32(St, n)
+            else:
+                Sp = apply_gate(S, Q, ch, sh)
+                St = truncate(Sp, delta, K)
+                S, cI = normalize(St, n)
             if on_gate is not None:
                 on_gate(g, S, cI)
             g += 1
@@ -181,9 +226,10 @@ def evolve(n: int, strings: Sequence[str], alphas: Sequence[float],
 
 def expect(S: Dict[str, float], strings: Iterable[str], coefs: Iterable[float]) -> float:
     """<O> = sum_j o_j a_{P_j} for O = sum_j o_j P_j (absent strings count 0)."""
-    return math.fsum(o * S.get(P, 0.0) for P, o in zip(strings, coefs))
+    return math.fsum(o * float(S.get(P, 0.0)) for P, o in zip(strings, coefs))
 
 
 def run_workload(w, **kw):
     """Convenience wrapper for an ``itpp_workloads.Workload``."""
+    kw.setdefault("precision", w.precision)
     return evolve(w.n, w.strings, w.alphas, w.schedule, w.dtau, w.n_steps, w.delta, w.K, **kw)
