@@ -53,6 +53,13 @@ typedef enum {
   ITPP_ERR_STATE = 6     /* call out of order (e.g. evolve before set_schedule) */
 } itpp_status;
 
+/* Stored coefficient type.  ITPP_F64: binary64 throughout.  ITPP_F32: the
+ * coefficients are binary32 and every product and sum of the propagation
+ * rule (Eq. ITPP_PropRules) is rounded to binary32 with cosh/sinh rounded to
+ * binary32 once per gate; the threshold and cap compare the exactly widened
+ * magnitudes; the division by the identity coefficient (Sec. II.C) is done
+ * in binary64 and rounded once to binary32; itpp_expect sums in binary64
+ * with compensation and itpp_export returns the binary32 values widened. */
 typedef enum { ITPP_F64 = 0, ITPP_F32 = 1 } itpp_precision;
 
 /* What to do when more than max_terms strings survive the threshold
@@ -62,7 +69,7 @@ typedef enum { ITPP_CAP_TOPK = 0, ITPP_CAP_FAIL = 1 } itpp_cap_policy;
 
 typedef struct {
   int32_t n_qubits;           /* 1..128 */
-  int32_t precision;          /* itpp_precision; ITPP_F64 only in this version */
+  int32_t precision;          /* itpp_precision */
   double threshold;           /* delta >= 0, keep |c| > delta (Sec. II.B); delta < 1 */
   int64_t max_terms;          /* K >= 1: the identity plus at most K-1 others */
   int32_t cap_policy;         /* itpp_cap_policy */

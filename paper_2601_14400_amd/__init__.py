@@ -12,6 +12,7 @@ __all__ = ["Engine", "ItppError", "load_library", "strings_to_words", "words_to_
 
 def engine_for(w, **kw) -> Engine:
     """Engine configured with a workload's Hamiltonian, schedule, threshold and cap."""
+    kw.setdefault("precision", w.precision)
     e = Engine(w.n, w.delta, w.K, **kw)
     e.set_hamiltonian(w.strings, w.alphas)
     e.set_schedule(w.schedule)

@@ -40,6 +40,7 @@ struct TermInfo {
 struct itpp_ctx_s {
   itpp_config cfg{};
   int n = 0, W = 1, NW = 2, nbits = 2;
+  int f32 = 0, coef_bytes = 8;  // stored coefficient type: binary32 or binary64
   hipStream_t stream = nullptr;
   int device = 0;
   int cus = 256;
@@ -189,7 +190,7 @@ itpp_status do_reset(itpp_ctx c) {
   c->cur = 0;
   c->par = 0;
   c->gpos = 0;
-  HIP_TRY(c, launch_init(c->NW, c->side[0], c->plan + 0, c->filt + 0, c->ctl, w0, c->stream));
+  HIP_TRY(c, launch_init(c->NW, c->f32, c->side[0], c->plan + 0, c->filt + 0, c->ctl, w0, c->stream));
   c->ready = true;
   return ITPP_OK;
 }
@@ -237,7 +238,8 @@ itpp_status itpp_create(const itpp_config* cfg, itpp_ctx* out) {
   if (!(cfg->threshold >= 0.0) || !std::isfinite(cfg->threshold) || cfg->threshold >= 1.0)
     return create_fail(ITPP_ERR_ARG, "threshold must be finite, >= 0 and < 1");
   if (cfg->max_terms < 1) return create_fail(ITPP_ERR_ARG, "max_terms must be >= 1");
-  if (cfg->precision != ITPP_F64) return create_fail(ITPP_ERR_ARG, "only ITPP_F64 is supported");
+  if (cfg->precision != ITPP_F64 && cfg->precision != ITPP_F32)
+    return create_fail(ITPP_ERR_ARG, "precision must be ITPP_F64 or ITPP_F32");
   if (cfg->cap_policy != ITPP_CAP_TOPK && cfg->cap_policy != ITPP_CAP_FAIL)
     return create_fail(ITPP_ERR_ARG, "unknown cap policy");
   int dev = 0;
@@ -257,6 +259,8 @@ itpp_status itpp_create(const itpp_config* cfg, itpp_ctx* out) {
   c->W = (c->n + 63) / 64;
   c->NW = 2 * c->W;
   c->nbits = 2 * c->n;
+  c->f32 = cfg->precision == ITPP_F32 ? 1 : 0;
+  c->coef_bytes = c->f32 ? 4 : 8;
   c->stream = static_cast<hipStream_t>(cfg->stream);
   c->device = dev;
   c->cus = prop.multiProcessorCount;
@@ -265,7 +269,7 @@ itpp_status itpp_create(const itpp_config* cfg, itpp_ctx* out) {
   uint64_t kmax = (uint64_t)cfg->max_terms;
   if (c->n <= 30) kmax = std::min<uint64_t>(kmax, 1ull << (2 * c->n));
   c->cap = 4 * kmax + 64;
-  const uint64_t elem_bytes = (uint64_t)c->NW * 8 + 8;
+  const uint64_t elem_bytes = (uint64_t)c->NW * 8 + (uint64_t)c->coef_bytes;
   const int tile = gate_tile(c->NW);
   c->status_cap = c->cap / (uint64_t)tile + 16;
   const uint64_t sel_cap = 2 * kmax + 64;
@@ -278,7 +282,11 @@ itpp_status itpp_create(const itpp_config* cfg, itpp_ctx* out) {
   bool ok = true;
   for (int s = 0; s < 2 && ok; ++s) {
     for (int q = 0; q < c->NW && ok; ++q) ok = dalloc(c, &c->side[s].kw[q], c->cap) == hipSuccess;
-    if (ok) ok = dalloc(c, &c->side[s].coef, c->cap) == hipSuccess;
+    if (ok) {
+      uint8_t* cb = nullptr;
+      ok = dalloc(c, &cb, c->cap * (uint64_t)c->coef_bytes) == hipSuccess;
+      c->side[s].coef = cb;
+    }
   }
   if (ok) ok = dalloc(c, &c->plan, 2) == hipSuccess;
   if (ok) ok = dalloc(c, &c->filt, 2) == hipSuccess;
@@ -487,10 +495,10 @@ static itpp_status enqueue_gate(itpp_ctx c, double dtau, bool spec) {
     HIP_TRY(c, next_event(c, &e2));
     HIP_TRY(c, hipEventRecord(e0, c->stream));
   }
-  HIP_TRY(c, launch_gate(c->NW, gp, c->side[in], c->side[out], c->plan + pin, c->plan + pout, c->filt + pin,
+  HIP_TRY(c, launch_gate(c->NW, c->f32, gp, c->side[in], c->side[out], c->plan + pin, c->plan + pout, c->filt + pin,
                          c->ctl, c->status, c->part, c->cus * gate_wgs_per_cu(), c->stream));
   if (c->timing) HIP_TRY(c, hipEventRecord(e1, c->stream));
-  HIP_TRY(c, launch_select(c->NW, c->side[out], c->plan + pout, c->filt + pin, c->filt + pout, c->plan + pin,
+  HIP_TRY(c, launch_select(c->NW, c->f32, c->side[out], c->plan + pout, c->filt + pin, c->filt + pout, c->plan + pin,
                            c->ctl, c->sel, rp, c->cfg.max_terms, c->cfg.cap_policy == ITPP_CAP_FAIL ? 1 : 0,
                            gp.spec, gp.serial, c->cus * 4, c->stream));
   if (c->timing) HIP_TRY(c, hipEventRecord(e2, c->stream));
@@ -576,7 +584,7 @@ static itpp_status run_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stat
     st->term_updates = h.term_updates - tu0;
     st->c_identity = f.cI;
     st->cap_hit = (int32_t)h.cap_hit;
-    st->alg_bytes = (h.alg_elems - ae0) * (double)(8 * c->NW + 8);
+    st->alg_bytes = (h.alg_elems - ae0) * (double)(8 * c->NW + c->coef_bytes);
     st->spec_gates = (int64_t)(h.spec_gates - sg0);
     st->spec_retries = retries;
   }
@@ -584,7 +592,7 @@ static itpp_status run_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stat
     Ctl h{};
     HIP_TRY(c, hipMemcpyAsync(&h, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    c->t_alg_bytes += (h.alg_elems - ae0) * (double)(8 * c->NW + 8);
+    c->t_alg_bytes += (h.alg_elems - ae0) * (double)(8 * c->NW + c->coef_bytes);
   }
   return ITPP_OK;
 }
@@ -664,7 +672,7 @@ itpp_status itpp_expect(itpp_ctx c, int32_t m, const uint64_t* x, const uint64_t
   RepPos rp{};
   rp.nbits = c->nbits;
   for (int b = 0; b < c->nbits; ++b) rp.pos[b] = (uint8_t)c->pos[b];
-  hipError_t e = launch_observe(c->NW, c->side[c->cur], c->plan + c->par, c->filt + c->par, rp, dx, dz, dc, m,
+  hipError_t e = launch_observe(c->NW, c->f32, c->side[c->cur], c->plan + c->par, c->filt + c->par, rp, dx, dz, dc, m,
                                 c->d_result, c->ctl, c->stream);
   double r = 0.0;
   if (e == hipSuccess) e = hipMemcpyAsync(&r, c->d_result, sizeof(double), hipMemcpyDeviceToHost, c->stream);
@@ -699,7 +707,7 @@ itpp_status itpp_export(itpp_ctx c, int64_t capacity, uint64_t* x, uint64_t* z, 
   RepPos rp{};
   rp.nbits = c->nbits;
   for (int b = 0; b < c->nbits; ++b) rp.pos[b] = (uint8_t)c->pos[b];
-  hipError_t e = launch_export(c->NW, c->side[c->cur], c->plan + c->par, c->filt + c->par, rp, dx, dz, dc, dn,
+  hipError_t e = launch_export(c->NW, c->f32, c->side[c->cur], c->plan + c->par, c->filt + c->par, rp, dx, dz, dc, dn,
                                (uint64_t)nt, c->cus * 4, c->stream);
   unsigned long long cnt = 0;
   std::vector<uint64_t> hx((size_t)nt * W), hz((size_t)nt * W);

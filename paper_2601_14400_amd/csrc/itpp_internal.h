@@ -103,9 +103,10 @@ constexpr int kStatusWords = 2 + 2 * kMaxClasses;
 typedef unsigned long long TileStatus;
 
 // Device arrays of one side of the ping-pong state buffers.
+// coef points to binary64 or binary32 values (the context's precision).
 struct Side {
   uint64_t* kw[kMaxKeyWords];
-  double* coef;
+  void* coef;
 };
 
 // Rep positions of the canonical bits of a stored state.
@@ -156,21 +157,21 @@ struct SelBuf {
 };
 
 // Host launchers (defined in itpp_kernels.hip).
-hipError_t launch_init(int nw, Side s0, Plan* plan, Filter* filt, Ctl* ctl, int w0, hipStream_t st);
+hipError_t launch_init(int nw, int f32, Side s0, Plan* plan, Filter* filt, Ctl* ctl, int w0, hipStream_t st);
 hipError_t launch_partition(int nw, const GateParams& gp, Side in, const Plan* plan_in, Ctl* ctl, uint64_t* part,
                             hipStream_t st);
-hipError_t launch_gate(int nw, const GateParams& gp, Side in, Side out, const Plan* plan_in,
+hipError_t launch_gate(int nw, int f32, const GateParams& gp, Side in, Side out, const Plan* plan_in,
                        Plan* plan_out, const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part,
                        int grid, hipStream_t st);
-hipError_t launch_select(int nw, Side out, const Plan* plan_out, const Filter* filt_in,
+hipError_t launch_select(int nw, int f32, Side out, const Plan* plan_out, const Filter* filt_in,
                          Filter* filt_out, Plan* plan_next, Ctl* ctl, SelBuf sel, const RepPos& rp,
                          int64_t K, int cap_fail, int spec, uint64_t serial, int grid, hipStream_t st);
 hipError_t launch_prepare(Plan* plan_out, Ctl* ctl, hipStream_t st);
 hipError_t launch_clear_status(TileStatus* status, uint64_t n, hipStream_t st);
-hipError_t launch_observe(int nw, Side s, const Plan* plan, const Filter* filt, const RepPos& rp,
+hipError_t launch_observe(int nw, int f32, Side s, const Plan* plan, const Filter* filt, const RepPos& rp,
                           const uint64_t* ox, const uint64_t* oz, const double* oc, int32_t m,
                           double* result, Ctl* ctl, hipStream_t st);
-hipError_t launch_export(int nw, Side s, const Plan* plan, const Filter* filt, const RepPos& rp,
+hipError_t launch_export(int nw, int f32, Side s, const Plan* plan, const Filter* filt, const RepPos& rp,
                          uint64_t* ex, uint64_t* ez, double* ec, unsigned long long* count,
                          uint64_t limit, int grid, hipStream_t st);
 int gate_tile(int nw);

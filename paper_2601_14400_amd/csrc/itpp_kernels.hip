@@ -173,6 +173,26 @@ __device__ __forceinline__ uint64_t abs_bits(double v) {
   return (uint64_t)__double_as_longlong(v) & 0x7fffffffffffffffull;
 }
 
+// Coefficient arithmetic of the two storage precisions.  Products and sums
+// are rounded to the storage type T; the division by the identity
+// coefficient is done in double and rounded once to T; magnitudes are
+// compared, histogrammed and selected as doubles (exact widening, so the
+// order is that of T).
+__device__ __forceinline__ double mul_rn(double a, double b) { return __dmul_rn(a, b); }
+__device__ __forceinline__ float mul_rn(float a, float b) { return __fmul_rn(a, b); }
+__device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
+__device__ __forceinline__ float add_rn(float a, float b) { return __fadd_rn(a, b); }
+__device__ __forceinline__ double abs_d(double v) { return fabs(v); }
+__device__ __forceinline__ double abs_d(float v) { return (double)fabsf(v); }
+template <typename T>
+__device__ __forceinline__ T normalised(T c, double cI) {
+  return (T)((double)c / cI);
+}
+template <typename T>
+__device__ __forceinline__ T* coefs(const Side& s) {
+  return static_cast<T*>(s.coef);
+}
+
 __device__ __forceinline__ int hist_bin(uint64_t bits) {
   const int64_t b = (int64_t)(bits >> kHistShift) - (int64_t)kHistBase;
   return b < 0 ? 0 : (b >= kHistBins ? kHistBins - 1 : (int)b);
@@ -411,13 +431,13 @@ __global__ __launch_bounds__(256) void partition_kernel(GateParams gp, Side in, 
 // run per output stream and next class; (3) a block scan turns run counts
 // into tile ranks, a look-back across tiles of the same join turns them into
 // region positions; (4) every element writes its outputs.
-template <int NW, int BLOCK, int TILE>
+template <int NW, int BLOCK, int TILE, typename T>
 struct GateSmem {
   static_assert(TILE + 1 < 4096, "tile counts are packed in 12-bit look-back fields");
   static constexpr int CAPT = TILE + 2;
   static constexpr int PER = (CAPT + BLOCK - 1) / BLOCK;
   uint64_t key[NW][CAPT];
-  double coef[CAPT];
+  T coef[CAPT];
   uint16_t info[CAPT];  // bit0 survive, bit1 commuting, bit2 paired, bit3 self, bits4-5 its class,
                         // bit6 branch, bits7-8 its class
   uint16_t partner[CAPT];
@@ -454,27 +474,28 @@ __device__ __forceinline__ Key<NW> lds_key(const uint64_t (*key)[TILE + 2], int 
 
 // New value of an element (Eq. ITPP_PropRules, then the branch of an
 // unpaired commuting string); neg: Q P = -R.
-__device__ __forceinline__ void values_from(double c, bool comm, bool paired, double cp, bool neg,
-                                            const GateParams& gp, double& vs, double& vb) {
-  vb = 0.0;
+template <typename T>
+__device__ __forceinline__ void values_from(T c, bool comm, bool paired, T cp, bool neg, T ch, T sh, T& vs,
+                                            T& vb) {
+  vb = (T)0;
   if (!comm) {
     vs = c;
     return;
   }
-  const double t1 = __dmul_rn(gp.ch, c);
+  const T t1 = mul_rn(ch, c);
   if (paired) {
-    double t2 = __dmul_rn(gp.sh, cp);
+    T t2 = mul_rn(sh, cp);
     if (!neg) t2 = -t2;
-    vs = __dadd_rn(t1, t2);
+    vs = add_rn(t1, t2);
   } else {
     vs = t1;
-    double t2 = __dmul_rn(gp.sh, c);
+    T t2 = mul_rn(sh, c);
     if (!neg) t2 = -t2;
     vb = t2;
   }
 }
 
-template <int NW, int BLOCK, int TILE>
+template <int NW, int BLOCK, int TILE, typename T>
 __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, Side out,
                                                       const Plan* __restrict__ plan_in,
                                                       Plan* __restrict__ plan_out,
@@ -482,7 +503,7 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
                                                       const uint64_t* __restrict__ part,
                                                       Ctl* __restrict__ ctl,
                                                       TileStatus* __restrict__ status) {
-  using Smem = GateSmem<NW, BLOCK, TILE>;
+  using Smem = GateSmem<NW, BLOCK, TILE, T>;
   constexpr int PER = Smem::PER;
   __shared__ Smem sm;
   const int tid = threadIdx.x;
@@ -490,6 +511,7 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
   // nothing at all (not even the plan prologue) after an error or a halt
   if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kErrNone || ctl->halt) return;
   const Filter fin = *filt_in;
+  const T ch = (T)gp.ch, sh = (T)gp.sh;
   const int nbits = gp.nbits;
   const int w = gp.w;
   const int ncls = 1 << w;
@@ -566,13 +588,13 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
       const bool isA = x < nAt;
       const uint64_t p = isA ? phys_sel(VA, i0 + x) : phys_sel(VB, j0 + (x - nAt));
       Key<NW> k = load_key<NW>(in, p);
-      const double cs = in.coef[p];
-      const bool sv = survives(k, cs, fin, gp.pos_in, nbits);
+      const T cs = coefs<T>(in)[p];
+      const bool sv = survives(k, (double)cs, fin, gp.pos_in, nbits);
       const bool comm = !anticommutes(k, gp);
       if (!isA) k = xor_top(k, nbits, w);  // B' = B xor Q lives in class cA's key space
 #pragma unroll
       for (int q = 0; q < NW; ++q) sm.key[q][x] = k.w[q];
-      sm.coef[x] = cs / fin.cI;
+      sm.coef[x] = normalised<T>(cs, fin.cI);
       sm.info[x] = (uint16_t)((sv ? 1 : 0) | (comm ? 2 : 0));
     }
     __syncthreads();
@@ -621,8 +643,8 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
           uint16_t rsx = 0, rbx = 0;
           if (sv) {
             const bool paired = (y >= 0) && (sm.info[y] & 1);
-            const double c = sm.coef[x];
-            const double cp = paired ? sm.coef[y] : 0.0;
+            const T c = sm.coef[x];
+            const T cp = paired ? sm.coef[y] : (T)0;
             const Key<NW> ownk = isA ? k : xor_top(k, nbits, w);
             bool neg = false;
             if (comm) {
@@ -631,10 +653,10 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
               neg = (e4 == 2);
               if (neg) inf |= 512u;
             }
-            double vs, vb;
-            values_from(c, comm, paired, cp, neg, gp, vs, vb);
-            const bool hs = fabs(vs) > tw;
-            const bool hb = comm && !paired && fabs(vb) > tw;
+            T vs, vb;
+            values_from<T>(c, comm, paired, cp, neg, ch, sh, vs, vb);
+            const bool hs = abs_d(vs) > tw;
+            const bool hb = comm && !paired && abs_d(vb) > tw;
             if (paired) {
               inf |= 4u;
               sm.partner[x] = (uint16_t)y;
@@ -851,9 +873,9 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
       const bool isA = x < nAt;
       const Key<NW> k = lds_key<NW, TILE>(sm.key, x);
       const bool paired = (inf >> 2) & 1;
-      double vs, vb;
-      values_from(sm.coef[x], (inf >> 1) & 1, paired, paired ? sm.coef[sm.partner[x]] : 0.0, (inf >> 9) & 1, gp,
-                  vs, vb);
+      T vs, vb;
+      values_from<T>(sm.coef[x], (inf >> 1) & 1, paired, paired ? sm.coef[sm.partner[x]] : (T)0, (inf >> 9) & 1,
+                     ch, sh, vs, vb);
       // next-rep keys: one bit move; the two outputs differ by this gate's mask
       Key<NW> mk = k;
       for (int mm = 0; mm < gp.w1; ++mm) mk = move_top(mk, gp.mv[mm], nbits);
@@ -873,12 +895,12 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
           atomicMax(&ctl->error, kErrCapacity);
         } else {
           store_key<NW>(out, pos, ks);
-          out.coef[pos] = vs;
+          coefs<T>(out)[pos] = vs;
           if (key_zero(ks)) {
-            ctl->cI_out = vs;
+            ctl->cI_out = (double)vs;
             ctl->have_cI = 1u;
           } else {
-            const uint64_t bits = abs_bits(vs);
+            const uint64_t bits = abs_bits((double)vs);
             if (bits >= win_hi) ++above;
             else if (bits >= win_lo) atomicAdd(&sm.fhist[(bits - win_lo) >> kFineShift], 1u);
             ++written;
@@ -896,8 +918,8 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
           atomicMax(&ctl->error, kErrCapacity);
         } else {
           store_key<NW>(out, pos, kb);
-          out.coef[pos] = vb;
-          const uint64_t bits = abs_bits(vb);
+          coefs<T>(out)[pos] = vb;
+          const uint64_t bits = abs_bits((double)vb);
           if (bits >= win_hi) ++above;
           else if (bits >= win_lo) atomicAdd(&sm.fhist[(bits - win_lo) >> kFineShift], 1u);
           ++written;
@@ -928,11 +950,11 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
 
 // ---------------------------------------------------------------------------
 // rho = I: one identity string with coefficient 1 (Algorithm 1 initial state).
-template <int NW>
+template <int NW, typename T>
 __global__ void init_kernel(Side s0, Plan* plan, Filter* filt, Ctl* ctl, int w0) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   for (int q = 0; q < NW; ++q) s0.kw[q][0] = 0ull;
-  s0.coef[0] = 1.0;
+  coefs<T>(s0)[0] = (T)1;
   Plan p = {};
   p.cnt[0][0] = 1;
   p.ncnt[0][0] = 1;
@@ -1128,7 +1150,7 @@ __global__ void prepare_kernel(Plan* plan_out, Ctl* ctl) {
 
 // Fallback when the K-th value is outside the fine window: full histogram of
 // the stored non-identity |c| values (16 bins per octave).
-template <int NW>
+template <int NW, typename T>
 __global__ __launch_bounds__(256) void select_coarse_hist(Side out, const Plan* plan, Ctl* ctl) {
   __shared__ uint32_t h[kHistBins];
   if (ctl->error || ctl->halt || !ctl->need_coarse) return;
@@ -1143,7 +1165,7 @@ __global__ __launch_bounds__(256) void select_coarse_hist(Side out, const Plan* 
       const uint64_t cnt = p.cnt[c][e];
       for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
         if (c == 0 && e == 0 && i == 0) continue;  // the identity is the first string of region (0,0)
-        atomicAdd(&h[hist_bin(abs_bits(out.coef[base + i]))], 1u);
+        atomicAdd(&h[hist_bin(abs_bits((double)coefs<T>(out)[base + i]))], 1u);
       }
     }
   __syncthreads();
@@ -1178,7 +1200,7 @@ __global__ __launch_bounds__(1024) void select_coarse_pick(Ctl* ctl) {
 
 // Collect the stored non-identity elements whose |c| bits lie in the
 // selected range.
-template <int NW>
+template <int NW, typename T>
 __global__ void select_collect(Side out, const Plan* plan, Ctl* ctl, SelBuf sel) {
   if (ctl->error || ctl->halt || ctl->sel_need == 0) return;
   const uint64_t lo = ctl->sel_lo, hi = ctl->sel_hi;
@@ -1191,7 +1213,7 @@ __global__ void select_collect(Side out, const Plan* plan, Ctl* ctl, SelBuf sel)
       const uint64_t cnt = p.cnt[c][e];
       for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
         const uint64_t idx = base + i;
-        const uint64_t b = abs_bits(out.coef[idx]);
+        const uint64_t b = abs_bits((double)coefs<T>(out)[idx]);
         if (b < lo || b >= hi) continue;
         Key<NW> k = load_key<NW>(out, idx);
         if (key_zero(k)) continue;
@@ -1311,7 +1333,7 @@ __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e
   e = __dadd_rn(__dsub_rn(a, __dsub_rn(s, bb)), __dsub_rn(b, bb));
 }
 
-template <int NW>
+template <int NW, typename T>
 __global__ __launch_bounds__(256) void observe_kernel(Side s, const Plan* plan, const Filter* filt,
                                                       RepPos rp, const uint64_t* ox, const uint64_t* oz,
                                                       const double* oc, int32_t m, double* result) {
@@ -1341,8 +1363,8 @@ __global__ __launch_bounds__(256) void observe_kernel(Side s, const Plan* plan, 
           hi = mid;
       }
       if (lo < p.base[c][e] + p.cnt[c][e] && key_eq(load_key<NW>(s, lo), k)) {
-        const double cs = s.coef[lo];
-        if (survives(k, cs, f, rp.pos, rp.nbits)) a = cs / f.cI;
+        const T cs = coefs<T>(s)[lo];
+        if (survives(k, (double)cs, f, rp.pos, rp.nbits)) a = (double)normalised<T>(cs, f.cI);
       }
     }
     double term = __dmul_rn(oc[j], a);
@@ -1368,7 +1390,7 @@ __global__ __launch_bounds__(256) void observe_kernel(Side s, const Plan* plan, 
 
 // Copy every surviving string (canonical x/z words, normalised coefficient)
 // to the export buffers in arbitrary order.
-template <int NW>
+template <int NW, typename T>
 __global__ void export_kernel(Side s, const Plan* plan, const Filter* filt, RepPos rp, uint64_t* ex,
                               uint64_t* ez, double* ec, unsigned long long* count, uint64_t limit) {
   const Plan& p = *plan;
@@ -1380,8 +1402,8 @@ __global__ void export_kernel(Side s, const Plan* plan, const Filter* filt, RepP
       for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.cnt[c][e]; i += stride) {
         const uint64_t idx = p.base[c][e] + i;
         Key<NW> k = load_key<NW>(s, idx);
-        const double cs = s.coef[idx];
-        if (!survives(k, cs, f, rp.pos, rp.nbits)) continue;
+        const T cs = coefs<T>(s)[idx];
+        if (!survives(k, (double)cs, f, rp.pos, rp.nbits)) continue;
         Key<NW> ck = to_canonical(k, rp.pos, rp.nbits);
         const unsigned long long slot = atomicAdd(count, 1ull);
         if (slot >= limit) continue;
@@ -1389,7 +1411,7 @@ __global__ void export_kernel(Side s, const Plan* plan, const Filter* filt, RepP
           ex[slot * W + q] = ck.w[q];
           ez[slot * W + q] = ck.w[W + q];
         }
-        ec[slot] = cs / f.cI;
+        ec[slot] = (double)normalised<T>(cs, f.cI);
       }
     }
 }
@@ -1422,11 +1444,31 @@ struct TileFor<4> {
 int gate_tile(int nw) { return nw == 2 ? TileFor<2>::value : TileFor<4>::value; }
 int gate_wgs_per_cu() { return 1024 / kBlock; }
 
-hipError_t launch_init(int nw, Side s0, Plan* plan, Filter* filt, Ctl* ctl, int w0, hipStream_t st) {
-  if (nw == 2)
-    hipLaunchKernelGGL(init_kernel<2>, dim3(1), dim3(64), 0, st, s0, plan, filt, ctl, w0);
-  else
-    hipLaunchKernelGGL(init_kernel<4>, dim3(1), dim3(64), 0, st, s0, plan, filt, ctl, w0);
+// Instantiations: key words (2: n <= 64, 4: n <= 128) x coefficient type.
+#define ITPP_DISPATCH(nw, f32, KERNEL_CALL)            \
+  do {                                                  \
+    if (nw == 2 && !f32) {                              \
+      constexpr int NWC = 2;                            \
+      using TC = double;                                \
+      KERNEL_CALL;                                      \
+    } else if (nw == 2) {                               \
+      constexpr int NWC = 2;                            \
+      using TC = float;                                 \
+      KERNEL_CALL;                                      \
+    } else if (!f32) {                                  \
+      constexpr int NWC = 4;                            \
+      using TC = double;                                \
+      KERNEL_CALL;                                      \
+    } else {                                            \
+      constexpr int NWC = 4;                            \
+      using TC = float;                                 \
+      KERNEL_CALL;                                      \
+    }                                                   \
+  } while (0)
+
+hipError_t launch_init(int nw, int f32, Side s0, Plan* plan, Filter* filt, Ctl* ctl, int w0, hipStream_t st) {
+  ITPP_DISPATCH(nw, f32,
+                hipLaunchKernelGGL((init_kernel<NWC, TC>), dim3(1), dim3(64), 0, st, s0, plan, filt, ctl, w0));
   return hipGetLastError();
 }
 
@@ -1442,15 +1484,13 @@ hipError_t launch_partition(int nw, const GateParams& gp, Side in, const Plan* p
   return hipGetLastError();
 }
 
-hipError_t launch_gate(int nw, const GateParams& gp, Side in, Side out, const Plan* plan_in,
+hipError_t launch_gate(int nw, int f32, const GateParams& gp, Side in, Side out, const Plan* plan_in,
                        Plan* plan_out, const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part,
                        int grid, hipStream_t st) {
-  if (nw == 2)
-    hipLaunchKernelGGL((gate_kernel<2, kBlock, TileFor<2>::value>), dim3(grid), dim3(kBlock), 0, st, gp, in, out,
-                       plan_in, plan_out, filt_in, (const uint64_t*)part, ctl, status);
-  else
-    hipLaunchKernelGGL((gate_kernel<4, kBlock, TileFor<4>::value>), dim3(grid), dim3(kBlock), 0, st, gp, in, out,
-                       plan_in, plan_out, filt_in, (const uint64_t*)part, ctl, status);
+  ITPP_DISPATCH(nw, f32,
+                hipLaunchKernelGGL((gate_kernel<NWC, kBlock, TileFor<NWC>::value, TC>), dim3(grid), dim3(kBlock),
+                                   0, st, gp, in, out, plan_in, plan_out, filt_in, (const uint64_t*)part, ctl,
+                                   status));
   return hipGetLastError();
 }
 
@@ -1459,47 +1499,36 @@ hipError_t launch_prepare(Plan* plan_out, Ctl* ctl, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_select(int nw, Side out, const Plan* plan_out, const Filter* filt_in,
+hipError_t launch_select(int nw, int f32, Side out, const Plan* plan_out, const Filter* filt_in,
                          Filter* filt_out, Plan* plan_next, Ctl* ctl, SelBuf sel, const RepPos& rp,
                          int64_t K, int cap_fail, int spec, uint64_t serial, int grid, hipStream_t st) {
   hipLaunchKernelGGL(select_decide, dim3(1), dim3(1024), 0, st, filt_in, filt_out, plan_next, ctl, K,
                      cap_fail, spec, serial);
-  if (nw == 2) {
-    hipLaunchKernelGGL(select_coarse_hist<2>, dim3(grid), dim3(256), 0, st, out, plan_out, ctl);
+  ITPP_DISPATCH(nw, f32, {
+    hipLaunchKernelGGL((select_coarse_hist<NWC, TC>), dim3(grid), dim3(256), 0, st, out, plan_out, ctl);
     hipLaunchKernelGGL(select_coarse_pick, dim3(1), dim3(1024), 0, st, ctl);
-    hipLaunchKernelGGL(select_collect<2>, dim3(grid), dim3(256), 0, st, out, plan_out, ctl, sel);
-    hipLaunchKernelGGL(select_exact<2>, dim3(1), dim3(1024), 0, st, out, filt_out, ctl, sel, rp);
-  } else {
-    hipLaunchKernelGGL(select_coarse_hist<4>, dim3(grid), dim3(256), 0, st, out, plan_out, ctl);
-    hipLaunchKernelGGL(select_coarse_pick, dim3(1), dim3(1024), 0, st, ctl);
-    hipLaunchKernelGGL(select_collect<4>, dim3(grid), dim3(256), 0, st, out, plan_out, ctl, sel);
-    hipLaunchKernelGGL(select_exact<4>, dim3(1), dim3(1024), 0, st, out, filt_out, ctl, sel, rp);
-  }
+    hipLaunchKernelGGL((select_collect<NWC, TC>), dim3(grid), dim3(256), 0, st, out, plan_out, ctl, sel);
+    hipLaunchKernelGGL(select_exact<NWC>, dim3(1), dim3(1024), 0, st, out, filt_out, ctl, sel, rp);
+  });
   return hipGetLastError();
 }
 
-hipError_t launch_observe(int nw, Side s, const Plan* plan, const Filter* filt, const RepPos& rp,
+hipError_t launch_observe(int nw, int f32, Side s, const Plan* plan, const Filter* filt, const RepPos& rp,
                           const uint64_t* ox, const uint64_t* oz, const double* oc, int32_t m,
                           double* result, Ctl* ctl, hipStream_t st) {
   (void)ctl;
-  if (nw == 2)
-    hipLaunchKernelGGL(observe_kernel<2>, dim3(1), dim3(256), 0, st, s, plan, filt, rp, ox, oz, oc, m,
-                       result);
-  else
-    hipLaunchKernelGGL(observe_kernel<4>, dim3(1), dim3(256), 0, st, s, plan, filt, rp, ox, oz, oc, m,
-                       result);
+  ITPP_DISPATCH(nw, f32,
+                hipLaunchKernelGGL((observe_kernel<NWC, TC>), dim3(1), dim3(256), 0, st, s, plan, filt, rp, ox, oz,
+                                   oc, m, result));
   return hipGetLastError();
 }
 
-hipError_t launch_export(int nw, Side s, const Plan* plan, const Filter* filt, const RepPos& rp,
+hipError_t launch_export(int nw, int f32, Side s, const Plan* plan, const Filter* filt, const RepPos& rp,
                          uint64_t* ex, uint64_t* ez, double* ec, unsigned long long* count, uint64_t limit,
                          int grid, hipStream_t st) {
-  if (nw == 2)
-    hipLaunchKernelGGL(export_kernel<2>, dim3(grid), dim3(256), 0, st, s, plan, filt, rp, ex, ez, ec, count,
-                       limit);
-  else
-    hipLaunchKernelGGL(export_kernel<4>, dim3(grid), dim3(256), 0, st, s, plan, filt, rp, ex, ez, ec, count,
-                       limit);
+  ITPP_DISPATCH(nw, f32,
+                hipLaunchKernelGGL((export_kernel<NWC, TC>), dim3(grid), dim3(256), 0, st, s, plan, filt, rp, ex,
+                                   ez, ec, count, limit));
   return hipGetLastError();
 }
 
