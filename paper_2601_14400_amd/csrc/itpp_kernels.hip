@@ -755,29 +755,42 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
         while (!done) {
           unsigned long long w0[LB], w1[LB];
           // position r*64 + lane is predecessor khi - (r*64 + lane): one
-          // coalesced load of 64 consecutive tiles per r
+          // coalesced load of 64 consecutive tiles per r.  All rows are in
+          // flight together; rows whose record carries an older epoch are
+          // read again until the predecessor has published.
+          uint32_t pend = 0;
 #pragma unroll
           for (int r = 0; r < LB; ++r) {
-            const int64_t k = khi - (int64_t)(r * 64 + lane);
             w0[r] = kInclReady;  // before the join's first tile: never needed, reads as ready with zero
             w1[r] = 0;
-            if (k < first) continue;
-            uint32_t spins = 0;
-            for (;;) {
-              const unsigned long long a0 = __hip_atomic_load(&status[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              const unsigned long long a1 = __hip_atomic_load(&status[SN + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              if ((a0 >> 52) == (tag12 >> 52) && (a1 >> 52) == (tag12 >> 52)) {
-                w0[r] = a0;
-                w1[r] = a1;
-                break;
+            if (khi - (int64_t)(r * 64 + lane) >= first) pend |= 1u << r;
+          }
+          uint32_t spins = 0;
+          while (pend) {
+#pragma unroll
+            for (int r = 0; r < LB; ++r) {
+              if ((pend >> r) & 1u) {
+                const int64_t k = khi - (int64_t)(r * 64 + lane);
+                w0[r] = __hip_atomic_load(&status[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                w1[r] = __hip_atomic_load(&status[SN + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
               }
-              if (++spins > (1u << 22)) {
-                atomicMax(&ctl->error, kErrSpin);
-                w0[r] = kInclReady;
-                break;
-              }
-              __builtin_amdgcn_s_sleep(1);
             }
+#pragma unroll
+            for (int r = 0; r < LB; ++r)
+              if (((pend >> r) & 1u) && (w0[r] >> 52) == (tag12 >> 52) && (w1[r] >> 52) == (tag12 >> 52))
+                pend &= ~(1u << r);
+            if (!pend) break;
+            if (++spins > (1u << 22)) {
+              atomicMax(&ctl->error, kErrSpin);
+#pragma unroll
+              for (int r = 0; r < LB; ++r)
+                if ((pend >> r) & 1u) {
+                  w0[r] = kInclReady;
+                  w1[r] = 0;
+                }
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
           }
           // nearest predecessor whose inclusive prefix is published
           uint32_t best = 64 * LB;
@@ -1289,32 +1302,44 @@ __global__ __launch_bounds__(1024) void select_exact(Side out, Filter* filt_out,
   }
   __syncthreads();
   const uint64_t nt = s_ntie;
-  // MSB-first selection of the need_eq-th smallest canonical key
+  // MSB-first radix selection (8-bit digits, X words before Z words) of
+  // the need_eq-th smallest canonical key
   constexpr int W = NW / 2;
   const int n = rp.nbits / 2;
+  const int ndig = (n + 7) / 8;  // digits per part; bits above n are zero in every key
   Key<NW> pre, msk;
   for (int q = 0; q < NW; ++q) pre.w[q] = msk.w[q] = 0;
-  uint32_t needk = need_eq;
+  uint64_t needk = need_eq;
   for (int part = 0; part < 2; ++part) {
-    for (int qb = n - 1; qb >= 0; --qb) {
-      const int word = part * W + (qb >> 6);
-      const uint64_t bit = 1ull << (qb & 63);
-      if (tid == 0) s_cnt0 = 0;
+    for (int d = ndig - 1; d >= 0; --d) {
+      const int word = part * W + (d >> 3);
+      const int sh = 8 * (d & 7);
+      for (int i = tid; i < 256; i += blockDim.x) h[i] = 0;
+      if (tid == 0) {
+        s_cnt0 = 0;
+        s_bin = -1;
+        s_above = 0;
+      }
       __syncthreads();
       uint32_t local = 0;
       for (uint64_t i = tid; i < nt; i += blockDim.x) {
         bool match = true;
         for (int q = 0; q < NW; ++q) match = match && ((sel.tie_keys[i * NW + q] & msk.w[q]) == pre.w[q]);
-        if (match && !(sel.tie_keys[i * NW + word] & bit)) ++local;
+        if (match) {
+          atomicAdd(&h[(sel.tie_keys[i * NW + word] >> sh) & 0xffull], 1u);
+          ++local;
+        }
       }
       if (local) atomicAdd(&s_cnt0, local);
       __syncthreads();
-      const uint32_t c0 = s_cnt0;
-      if (c0 < needk) {
-        needk -= c0;
-        pre.w[word] |= bit;
-      }
-      msk.w[word] |= bit;
+      // the needk-th smallest is the (M - needk + 1)-th largest of the M matches
+      const uint64_t M = s_cnt0;
+      find_from_top(h, 256, 0, M - needk + 1, scr, &s_bin, &s_above);
+      const int bsel = s_bin < 0 ? 0 : s_bin;
+      const uint64_t below = M - s_above - h[bsel];
+      needk -= below;
+      pre.w[word] |= (uint64_t)bsel << sh;
+      msk.w[word] |= 0xffull << sh;
       __syncthreads();
     }
   }
