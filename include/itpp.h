@@ -160,6 +160,39 @@ itpp_status itpp_num_terms(itpp_ctx ctx, int64_t* out);
 itpp_status itpp_export(itpp_ctx ctx, int64_t capacity, uint64_t* x, uint64_t* z, double* coef,
                         int64_t* n_out);
 
+/* Reverse sweep (derivatives of an observable with the truncation support
+ * held fixed).  The forward map of Algorithm 1 is differentiated gate by
+ * gate: for the division by the identity coefficient b_I,
+ * dL/db_P = lambda'_P / b_I minus, at the identity only, sum_R lambda'_R a'_R
+ * / b_I; the kept set restricts that vector; the gate rule of Eq.
+ * ITPP_PropRules gives lambda_P = ch lambda_u[P] - sigma sh lambda_u[R] for a
+ * commuting P (Q P = sigma R) and lambda_P = lambda_u[P] otherwise, and
+ * dL/dtheta = sum over commuting P of a_P (sh lambda_u[P] - sigma ch
+ * lambda_u[R]).  With theta = alpha_k m dtau the chain rule gives dL/dalpha_k
+ * and dL/ddtau.
+ *
+ * itpp_set_adjoint: every_steps > 0 makes the following forward runs store a
+ * packed copy of the state every every_steps Trotter steps (and run without
+ * speculation, so recomputation reproduces every stored layout);
+ * workspace_bytes bounds the device memory of one itpp_backward call for its
+ * recomputed states (0: 70% of the free device memory).  ITPP_F64 contexts
+ * only (ITPP_ERR_ARG otherwise).  Takes effect for the gates applied after
+ * the next reset or set_schedule. */
+itpp_status itpp_set_adjoint(itpp_ctx ctx, int32_t every_steps, int64_t workspace_bytes);
+
+/* For L = sum_j coef[j] a_{P_j} of the current state (strings as in
+ * itpp_expect): *value = L, d_alpha[k] = dL/dalpha_k for every Hamiltonian
+ * term (n_terms doubles, zero for identity terms and unscheduled terms),
+ * *d_dtau = dL/ddtau, and, if d_theta is not NULL, dL/dtheta for every
+ * elementary gate applied since the last reset (in order).  Requires a
+ * forward run since the last reset with itpp_set_adjoint enabled and one
+ * dtau (ITPP_ERR_STATE otherwise).  Between the stored copies the states are
+ * recomputed (sub-checkpoints every ~sqrt(segment) gates); ITPP_ERR_OOM if
+ * the workspace cannot hold them.  The current state is the same after the
+ * call; after an error it needs a reset. */
+itpp_status itpp_backward(itpp_ctx ctx, int32_t n_strings, const uint64_t* x, const uint64_t* z,
+                          const double* coef, double* value, double* d_alpha, double* d_dtau, double* d_theta);
+
 /* Engine options (results do not depend on them; only speed does).
  *  ITPP_OPT_SPECULATION (default 1): once the cap binds, a gate writes only
  *    the strings above a margin below the K-th value predicted from the

@@ -22,7 +22,8 @@ STATUS = {0: "ITPP_OK", 1: "ITPP_ERR_ARG", 2: "ITPP_ERR_OOM", 3: "ITPP_ERR_CAP",
 # Every entry point declared in include/itpp.h.
 EXPORTED = ["itpp_create", "itpp_destroy", "itpp_set_hamiltonian", "itpp_set_schedule",
             "itpp_reset", "itpp_evolve", "itpp_evolve_gates", "itpp_expect", "itpp_num_terms", "itpp_export",
-            "itpp_set_option", "itpp_set_timing", "itpp_get_timing", "itpp_last_error", "itpp_version"]
+            "itpp_set_adjoint", "itpp_backward", "itpp_set_option", "itpp_set_timing", "itpp_get_timing",
+            "itpp_last_error", "itpp_version"]
 
 
 class ItppConfig(ctypes.Structure):
@@ -81,6 +82,8 @@ def load_library(path: Optional[str] = None):
     lib.itpp_expect.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(dbl)]
     lib.itpp_num_terms.argtypes = [vp, ctypes.POINTER(i64)]
     lib.itpp_export.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(i64)]
+    lib.itpp_set_adjoint.argtypes = [vp, i32, i64]
+    lib.itpp_backward.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(dbl), vp, ctypes.POINTER(dbl), vp]
     lib.itpp_set_option.argtypes = [vp, i32, dbl]
     lib.itpp_set_timing.argtypes = [vp, i32]
     lib.itpp_get_timing.argtypes = [vp, ctypes.POINTER(ItppTiming)]
@@ -147,6 +150,8 @@ class Engine:
         self._lib = load_library()
         self.n = int(n_qubits)
         self.W = (self.n + 63) // 64
+        self.n_terms = 0
+        self.gates_since_reset = 0
         cfg = ItppConfig()
         cfg.n_qubits = self.n
         cfg.precision = {"f64": 0, "f32": 1}[precision]
@@ -179,6 +184,8 @@ class Engine:
             pass
 
     def set_hamiltonian(self, strings: Sequence[str], alphas: Sequence[float]):
+        self.n_terms = len(strings)
+        self.gates_since_reset = 0
         x, z = strings_to_words(strings, self.n)
         a = np.ascontiguousarray(alphas, dtype=np.float64)
         self._check(self._lib.itpp_set_hamiltonian(self._h, len(strings), x.ctypes.data,
@@ -188,19 +195,44 @@ class Engine:
         ti = np.ascontiguousarray([k for k, _ in schedule], dtype=np.int32)
         mu = np.ascontiguousarray([m for _, m in schedule], dtype=np.float64)
         self._check(self._lib.itpp_set_schedule(self._h, len(schedule), ti.ctypes.data, mu.ctypes.data))
+        self.gates_since_reset = 0
 
     def reset(self):
         self._check(self._lib.itpp_reset(self._h))
+        self.gates_since_reset = 0
 
     def evolve(self, dtau: float, n_steps: int) -> Dict[str, float]:
         st = ItppStats()
         self._check(self._lib.itpp_evolve(self._h, float(dtau), int(n_steps), ctypes.byref(st)))
+        self.gates_since_reset += st.n_gates
         return self._stats(st)
 
     def evolve_gates(self, dtau: float, n_gates: int) -> Dict[str, float]:
         st = ItppStats()
         self._check(self._lib.itpp_evolve_gates(self._h, float(dtau), int(n_gates), ctypes.byref(st)))
+        self.gates_since_reset += st.n_gates
         return self._stats(st)
+
+    def set_adjoint(self, every_steps: int, workspace_bytes: int = 0):
+        """Store forward checkpoints every ``every_steps`` Trotter steps so
+        that ``backward`` can run (takes effect from the next reset)."""
+        self._check(self._lib.itpp_set_adjoint(self._h, int(every_steps), int(workspace_bytes)))
+
+    def backward(self, strings: Sequence[str], coefs: Sequence[float], want_theta: bool = False):
+        """``L = sum_j coefs[j] a[strings[j]]`` and its derivatives with the
+        truncation support held fixed: ``(L, dL/dalpha per term, dL/ddtau,
+        dL/dtheta per gate or None)``."""
+        x, z = strings_to_words(strings, self.n)
+        c = np.ascontiguousarray(coefs, dtype=np.float64)
+        val = ctypes.c_double()
+        dd = ctypes.c_double()
+        da = np.zeros(max(self.n_terms, 1), dtype=np.float64)
+        dth = np.zeros(max(self.gates_since_reset, 1), dtype=np.float64) if want_theta else None
+        self._check(self._lib.itpp_backward(self._h, len(strings), x.ctypes.data, z.ctypes.data, c.ctypes.data,
+                                            ctypes.byref(val), da.ctypes.data, ctypes.byref(dd),
+                                            dth.ctypes.data if dth is not None else None))
+        return (float(val.value), da[: self.n_terms], float(dd.value),
+                dth[: self.gates_since_reset] if dth is not None else None)
 
     @staticmethod
     def _stats(st):

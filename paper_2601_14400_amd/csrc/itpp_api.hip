@@ -35,6 +35,19 @@ struct TermInfo {
   int aQ = 0;
 };
 
+// A stored state in the packed layout (regions back to back), with the
+// host data needed to continue the schedule from it.
+struct Snapshot {
+  void* owned = nullptr;  // allocation owned by the snapshot (forward checkpoints), else arena memory
+  Side side{};
+  Plan* plan = nullptr;
+  Filter* filt = nullptr;
+  uint64_t count = 0;
+  std::vector<int> pos;
+  int gpos = 0;
+  int64_t gate = 0;  // gates applied before this state since the last reset
+};
+
 }  // namespace
 
 struct itpp_ctx_s {
@@ -78,6 +91,13 @@ struct itpp_ctx_s {
   size_t ev_used = 0;
   double t_gate_ms = 0.0, t_sel_ms = 0.0, t_alg_bytes = 0.0;
   int64_t t_gates = 0;
+  // reverse sweep
+  int32_t ckpt_every = 0;       // Trotter steps between forward checkpoints (0: off)
+  int64_t adj_workspace = 0;    // bytes for the reverse sweep's snapshots (0: automatic)
+  int64_t fwd_gates = 0;        // gates applied since the last reset
+  double fwd_dtau = 0.0;        // their common dtau
+  bool fwd_valid = true;        // false once the gates since reset cannot be replayed
+  std::vector<Snapshot> ckpts;  // forward checkpoints
 };
 
 namespace {
@@ -173,6 +193,76 @@ hipError_t dalloc(itpp_ctx c, T** p, size_t count) {
   return e;
 }
 
+void free_ckpts(itpp_ctx c) {
+  for (Snapshot& s : c->ckpts)
+    if (s.owned) (void)hipFree(s.owned);
+  c->ckpts.clear();
+}
+
+static_assert(sizeof(Plan) <= 512 && sizeof(Filter) <= 512, "snapshot header layout");
+
+// Bytes of a packed snapshot of `count` elements (plan and filter first).
+uint64_t snapshot_bytes(itpp_ctx c, uint64_t count) {
+  const uint64_t head = 1024;
+  const uint64_t words = ((count * 8 + 255) / 256) * 256;
+  const uint64_t cb = ((count * (uint64_t)c->coef_bytes + 255) / 256) * 256;
+  return head + (uint64_t)c->NW * words + cb;
+}
+
+// Element count of the stored state (host read of its plan).
+hipError_t state_count(itpp_ctx c, uint64_t* out) {
+  Plan p{};
+  hipError_t e = hipMemcpyAsync(&p, c->plan + c->par, sizeof(Plan), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return e;
+  uint64_t n = 0;
+  for (int a = 0; a < (1 << p.wc); ++a)
+    for (int b = 0; b < (1 << p.we); ++b) n += p.cnt[a][b];
+  *out = n;
+  return hipSuccess;
+}
+
+// Pack the stored state into `mem` (snapshot_bytes(count) bytes).
+hipError_t write_snapshot(itpp_ctx c, Snapshot& s, void* mem, uint64_t count) {
+  uint8_t* m = static_cast<uint8_t*>(mem);
+  s.plan = reinterpret_cast<Plan*>(m);
+  s.filt = reinterpret_cast<Filter*>(m + 512);
+  s.count = count;
+  uint8_t* q = m + 1024;
+  const uint64_t words = ((count * 8 + 255) / 256) * 256;
+  for (int w = 0; w < kMaxKeyWords; ++w) s.side.kw[w] = nullptr;
+  for (int w = 0; w < c->NW; ++w) {
+    s.side.kw[w] = reinterpret_cast<uint64_t*>(q);
+    q += words;
+  }
+  s.side.coef = q;
+  s.pos = c->pos;
+  s.gpos = c->gpos;
+  s.gate = c->fwd_gates;
+  hipError_t e = launch_pack(c->NW, c->f32, c->side[c->cur], c->plan + c->par, s.side, s.plan, c->cus * 4,
+                             c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s.filt, c->filt + c->par, sizeof(Filter), hipMemcpyDeviceToDevice, c->stream);
+  return e;
+}
+
+// Make a snapshot the stored state again.
+hipError_t restore_snapshot(itpp_ctx c, const Snapshot& s) {
+  hipError_t e = hipSuccess;
+  for (int w = 0; w < c->NW && e == hipSuccess; ++w)
+    if (s.count) e = hipMemcpyAsync(c->side[c->cur].kw[w], s.side.kw[w], s.count * 8, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess && s.count)
+    e = hipMemcpyAsync(c->side[c->cur].coef, s.side.coef, s.count * (uint64_t)c->coef_bytes, hipMemcpyDeviceToDevice,
+                       c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->plan + c->par, s.plan, sizeof(Plan), hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->filt + c->par, s.filt, sizeof(Filter), hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = launch_prepare(c->plan + (c->par ^ 1), c->ctl, c->stream);
+  c->pos = s.pos;
+  c->gpos = s.gpos;
+  c->fwd_gates = s.gate;
+  return e;
+}
+
 // Initial rep: identity permutation with the first gate's flip bits on top.
 void reset_rep(itpp_ctx c) {
   c->pos.resize(c->nbits);
@@ -185,6 +275,10 @@ void reset_rep(itpp_ctx c) {
 
 itpp_status do_reset(itpp_ctx c) {
   reset_rep(c);
+  free_ckpts(c);
+  c->fwd_gates = 0;
+  c->fwd_dtau = 0.0;
+  c->fwd_valid = true;
   int w0 = 0;
   if (!c->glist.empty()) w0 = (int)c->terms[c->sched_term[c->glist[0]]].F.size();
   c->cur = 0;
@@ -324,6 +418,7 @@ itpp_status itpp_create(const itpp_config* cfg, itpp_ctx* out) {
 itpp_status itpp_destroy(itpp_ctx ctx) {
   if (!ctx) return ITPP_OK;
   (void)hipStreamSynchronize(ctx->stream);
+  free_ckpts(ctx);
   free_all(ctx);
   delete ctx;
   return ITPP_OK;
@@ -419,17 +514,17 @@ itpp_status itpp_evolve_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_sta
   return run_gates(c, dtau, n_gates, st);
 }
 
-// Plan and enqueue the next elementary gate of the schedule (asynchronous).
-static itpp_status enqueue_gate(itpp_ctx c, double dtau, bool spec) {
+// Parameters of gate i of the schedule's gate list for a state in rep `pos`;
+// pos1 receives the rep of its output and rp the output rep positions.
+static itpp_status build_gate(itpp_ctx c, int i, const std::vector<int>& pos, double dtau, bool spec,
+                              GateParams& gp, std::vector<int>& pos1, RepPos& rp) {
   const int G = (int)c->glist.size();
   const int nbits = c->nbits;
-  const int i = c->gpos;
   const int sg = c->glist[i];
   const TermInfo& t = c->terms[c->sched_term[sg]];
   const TermInfo& t1 = c->terms[c->sched_term[c->glist[(i + 1) % G]]];
   const TermInfo& t2 = c->terms[c->sched_term[c->glist[(i + 2) % G]]];
   const double theta = t.alpha * c->sched_mult[sg] * dtau;
-  GateParams gp;
   std::memset(&gp, 0, sizeof(gp));
   gp.ch = std::cosh(theta);
   gp.sh = std::sinh(theta);
@@ -438,22 +533,22 @@ static itpp_status enqueue_gate(itpp_ctx c, double dtau, bool spec) {
   gp.w1 = (int)t1.F.size();
   gp.w2 = (int)t2.F.size();
   for (int b : t.cbits) {
-    const int p = c->pos[b];
+    const int p = pos[b];
     gp.cmask[p >> 6] |= 1ull << (p & 63);
   }
   gp.nsup = t.nsup;
   gp.aQ = t.aQ & 3;
   for (int j = 0; j < t.nsup; ++j) {
-    gp.px[j] = c->pos[t.sup[j]];
-    gp.pz[j] = c->pos[c->n + t.sup[j]];
+    gp.px[j] = pos[t.sup[j]];
+    gp.pz[j] = pos[c->n + t.sup[j]];
     gp.qx[j] = t.qx[j];
     gp.qz[j] = t.qz[j];
   }
   for (int k = 0; k < gp.w; ++k)
-    if (c->pos[t.F[k]] != nbits - gp.w + k) return fail(c, ITPP_ERR_DEVICE, "internal error: rep invariant");
-  std::vector<int> pos1 = c->pos;
+    if (pos[t.F[k]] != nbits - gp.w + k) return fail(c, ITPP_ERR_DEVICE, "internal error: rep invariant");
+  pos1 = pos;
   for (int m = 0; m < gp.w1; ++m) {
-    gp.epos[m] = c->pos[t1.F[m]];
+    gp.epos[m] = pos[t1.F[m]];
     move_top(pos1, t1.F[m], nbits, &gp.mv[m]);
   }
   gp.ov = 0;
@@ -462,7 +557,7 @@ static itpp_status enqueue_gate(itpp_ctx c, double dtau, bool spec) {
   gp.ovf = 0;
   for (int b = 0; b < gp.w2; ++b) {
     gp.fpos[b] = pos1[t2.F[b]];
-    gp.fposg[b] = c->pos[t2.F[b]];
+    gp.fposg[b] = pos[t2.F[b]];
     if (std::find(t.F.begin(), t.F.end(), t2.F[b]) != t.F.end()) gp.ovf |= 1 << b;
   }
   for (int k = 0; k < gp.w; ++k) {
@@ -480,10 +575,22 @@ static itpp_status enqueue_gate(itpp_ctx c, double dtau, bool spec) {
   gp.spec = spec ? 1 : 0;
   gp.spec_mult = c->spec_mult;
   gp.serial = c->serial++;
-  for (int b = 0; b < nbits; ++b) gp.pos_in[b] = (uint8_t)c->pos[b];
-  RepPos rp{};
+  for (int b = 0; b < nbits; ++b) gp.pos_in[b] = (uint8_t)pos[b];
+  std::memset(&rp, 0, sizeof(rp));
   rp.nbits = nbits;
   for (int b = 0; b < nbits; ++b) rp.pos[b] = (uint8_t)pos1[b];
+  return ITPP_OK;
+}
+
+// Plan and enqueue the next elementary gate of the schedule (asynchronous).
+static itpp_status enqueue_gate(itpp_ctx c, double dtau, bool spec) {
+  const int G = (int)c->glist.size();
+  const int i = c->gpos;
+  GateParams gp;
+  std::vector<int> pos1;
+  RepPos rp;
+  itpp_status bs = build_gate(c, i, c->pos, dtau, spec, gp, pos1, rp);
+  if (bs != ITPP_OK) return bs;
   const int in = c->cur, out = c->cur ^ 1;
   const int pin = c->par, pout = c->par ^ 1;
   HIP_TRY(c, launch_partition(c->NW, gp, c->side[in], c->plan + pin, c->ctl, c->part, c->stream));
@@ -536,16 +643,45 @@ static itpp_status run_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stat
   int64_t done = 0;
   bool nospec_next = false;
   std::vector<HostSnap> snaps;
+  if (n_gates > 0 && G > 0) {
+    if (c->fwd_gates == 0) {
+      c->fwd_dtau = dtau;
+    } else if (dtau != c->fwd_dtau) {
+      c->fwd_valid = false;  // the reverse sweep assumes one dtau since reset
+      free_ckpts(c);
+    }
+  }
+  const int64_t E = (int64_t)c->ckpt_every * G;
   // Gates are enqueued in batches; after each batch the host checks whether
   // a speculative gate asked to be redone (all kernels after it were no-ops,
   // so that gate's input is intact) and replays from there without
   // speculation for that gate.
   while (done < n_gates && G > 0) {
-    const int64_t batch = std::min<int64_t>(n_gates - done, kSyncEvery);
+    int64_t batch = std::min<int64_t>(n_gates - done, kSyncEvery);
+    if (E > 0 && c->fwd_valid) {
+      // forward checkpoint of the state before gate fwd_gates, every E gates
+      if (c->fwd_gates % E == 0 && (int64_t)c->ckpts.size() == c->fwd_gates / E) {
+        uint64_t cnt = 0;
+        HIP_TRY(c, state_count(c, &cnt));
+        void* mem = nullptr;
+        if (hipMalloc(&mem, snapshot_bytes(c, cnt)) != hipSuccess) {
+          (void)hipGetLastError();
+          return fail(c, ITPP_ERR_OOM, "no device memory for a forward checkpoint");
+        }
+        Snapshot sn;
+        sn.owned = mem;
+        hipError_t he = write_snapshot(c, sn, mem, cnt);
+        c->ckpts.push_back(sn);
+        if (he != hipSuccess) return hip_fail(c, he, "forward checkpoint");
+      }
+      batch = std::min<int64_t>(batch, E - c->fwd_gates % E);
+    }
     snaps.clear();
     for (int64_t b = 0; b < batch; ++b) {
       snaps.push_back(HostSnap{c->pos, c->cur, c->par, c->gpos, c->serial, c->ev_used});
-      const bool spec = c->speculate && !(b == 0 && nospec_next);
+      // with checkpoints the forward writes exactly what a recomputation
+      // writes (no speculation), so stored states pack to the same layout
+      const bool spec = c->speculate && E == 0 && !(b == 0 && nospec_next);
       itpp_status s = enqueue_gate(c, dtau, spec);
       if (s != ITPP_OK) return s;
     }
@@ -566,11 +702,13 @@ static itpp_status run_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stat
       if (c->timing) c->ev_used = std::min(c->ev_used, sn.ev_used + 3);
       HIP_TRY(c, launch_prepare(c->plan + (c->par ^ 1), c->ctl, c->stream));
       done += idx;
+      c->fwd_gates += idx;
       nospec_next = true;
       ++retries;
       continue;
     }
     done += batch;
+    c->fwd_gates += batch;
   }
   c->retries_total += retries;
   if (st) {
@@ -741,6 +879,273 @@ itpp_status itpp_export(itpp_ctx c, int64_t capacity, uint64_t* x, uint64_t* z, 
   }
   *n_out = nt;
   return ITPP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct Arena {
+  uint8_t* base = nullptr;
+  uint64_t size = 0, top = 0;
+  void* take(uint64_t b) {
+    b = (b + 255) & ~255ull;
+    if (top + b > size) return nullptr;
+    void* p = base + top;
+    top += b;
+    return p;
+  }
+};
+
+// Snapshot of the stored state taken from the arena.
+itpp_status snap_in_arena(itpp_ctx c, Arena& ar, Snapshot& s) {
+  uint64_t cnt = 0;
+  HIP_TRY(c, state_count(c, &cnt));
+  void* mem = ar.take(snapshot_bytes(c, cnt));
+  if (!mem)
+    return fail(c, ITPP_ERR_OOM,
+                "reverse-sweep workspace too small: raise it or checkpoint more often (itpp_set_adjoint)");
+  HIP_TRY(c, write_snapshot(c, s, mem, cnt));
+  return ITPP_OK;
+}
+
+// Recompute one gate without speculation (the layout the reverse sweep replays).
+itpp_status replay_gate(itpp_ctx c) {
+  itpp_status st = enqueue_gate(c, c->fwd_dtau, false);
+  if (st != ITPP_OK) return st;
+  ++c->fwd_gates;
+  return ITPP_OK;
+}
+
+struct AdjBuffers {
+  double* lam[2];
+  double* sdev;     // [2]
+  double* part;     // 4 per tile
+  uint64_t* ntiles;
+  double* dtheta;   // per gate since reset
+};
+
+// Reverse step of gate g from its input snapshot Sin and output snapshot Sout.
+itpp_status adjoint_gate(itpp_ctx c, int64_t g, const Snapshot& Sin, const Snapshot& Sout, AdjBuffers& B, int cur) {
+  const int G = (int)c->glist.size();
+  const int i = (int)(g % G);
+  if (Sin.gpos != i) return fail(c, ITPP_ERR_DEVICE, "internal error: snapshot out of step");
+  GateParams gp;
+  std::vector<int> pos1;
+  RepPos rp;
+  itpp_status bs = build_gate(c, i, Sin.pos, c->fwd_dtau, false, gp, pos1, rp);
+  if (bs != ITPP_OK) return bs;
+  HIP_TRY(c, launch_partition(c->NW, gp, Sin.side, Sin.plan, c->ctl, c->part, c->stream));
+  AdjArgs a{};
+  a.lam_out = B.lam[cur];
+  a.lam_in = B.lam[cur ^ 1];
+  a.plan_next = Sout.plan;
+  a.filt_next = Sout.filt;
+  a.s_in = B.sdev + cur;
+  a.part = B.part;
+  a.ntiles = B.ntiles;
+  a.lam_out_len = Sout.count;
+  HIP_TRY(c, launch_adjoint_gate(c->NW, gp, Sin.side, Sin.plan, c->plan + (c->par ^ 1), Sin.filt, c->ctl, c->status,
+                                 c->part, a, c->cus * gate_wgs_per_cu(), c->stream));
+  HIP_TRY(c, launch_adj_reduce(B.part, B.ntiles, B.dtheta + g, B.sdev + (cur ^ 1), c->ctl, c->stream));
+  return ITPP_OK;
+}
+
+// Compensated sum (Neumaier) on the host.
+struct HostSum {
+  double s = 0.0, c = 0.0;
+  void add(double v) {
+    const double t = s + v;
+    if (std::fabs(s) >= std::fabs(v))
+      c += (s - t) + v;
+    else
+      c += (v - t) + s;
+    s = t;
+  }
+  double value() const { return s + c; }
+};
+
+itpp_status backward_impl(itpp_ctx c, int32_t m, const uint64_t* dx, const uint64_t* dz, const double* dc,
+                          double* value, double* d_alpha, double* d_dtau, double* d_theta, Arena& ar,
+                          AdjBuffers& B) {
+  const int64_t Gtot = c->fwd_gates;
+  const int nck = (int)c->ckpts.size();
+  // the final state: packed copy (restored at the end), L and the seed lambda
+  Snapshot SF;
+  itpp_status st = snap_in_arena(c, ar, SF);
+  if (st != ITPP_OK) return st;
+  RepPos rpF{};
+  rpF.nbits = c->nbits;
+  for (int b = 0; b < c->nbits; ++b) rpF.pos[b] = (uint8_t)SF.pos[b];
+  HIP_TRY(c, launch_observe(c->NW, c->f32, SF.side, SF.plan, SF.filt, rpF, dx, dz, dc, m, B.sdev, c->ctl, c->stream));
+  HIP_TRY(c, hipMemsetAsync(B.lam[0], 0, std::max<uint64_t>(SF.count, 1) * sizeof(double), c->stream));
+  if (m > 0) HIP_TRY(c, launch_seed(c->NW, SF.side, SF.plan, SF.filt, rpF, dx, dz, dc, m, B.lam[0], c->stream));
+  HIP_TRY(c, hipMemcpyAsync(value, B.sdev, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  int cur = 0;
+  const uint64_t keep_top = ar.top;
+  for (int k = nck - 1; k >= 0; --k) {
+    const int64_t a = c->ckpts[k].gate;
+    const int64_t b = (k + 1 < nck) ? c->ckpts[k + 1].gate : Gtot;
+    if (b <= a) continue;
+    const int64_t L = b - a;
+    int64_t sblk = (int64_t)std::ceil(std::sqrt((double)L));
+    if (sblk < 1) sblk = 1;
+    ar.top = keep_top;
+    // sub-checkpoints every sblk gates of the segment
+    std::vector<Snapshot> subs;
+    Snapshot s0 = c->ckpts[k];
+    s0.owned = nullptr;
+    subs.push_back(s0);
+    HIP_TRY(c, restore_snapshot(c, c->ckpts[k]));
+    for (int64_t g = a; g < b - 1; ++g) {
+      st = replay_gate(c);
+      if (st != ITPP_OK) return st;
+      if ((c->fwd_gates - a) % sblk == 0) {
+        Snapshot sn;
+        st = snap_in_arena(c, ar, sn);
+        if (st != ITPP_OK) return st;
+        subs.push_back(sn);
+      }
+    }
+    st = check_error(c);
+    if (st != ITPP_OK) return st;
+    const uint64_t sub_top = ar.top;
+    const int64_t nblk = (L + sblk - 1) / sblk;
+    for (int64_t q = nblk - 1; q >= 0; --q) {
+      ar.top = sub_top;
+      const int64_t m0 = a + q * sblk, m1 = std::min<int64_t>(b, m0 + sblk);
+      HIP_TRY(c, restore_snapshot(c, subs[q]));
+      std::vector<Snapshot> sn(m1 - m0 + 1);
+      for (int64_t g = m0; g <= m1; ++g) {
+        st = snap_in_arena(c, ar, sn[g - m0]);
+        if (st != ITPP_OK) return st;
+        if (g < m1) {
+          st = replay_gate(c);
+          if (st != ITPP_OK) return st;
+        }
+      }
+      for (int64_t g = m1 - 1; g >= m0; --g) {
+        st = adjoint_gate(c, g, sn[g - m0], sn[g - m0 + 1], B, cur);
+        if (st != ITPP_OK) return st;
+        cur ^= 1;
+      }
+      st = check_error(c);
+      if (st != ITPP_OK) return st;
+    }
+  }
+  // results
+  std::vector<double> dth((size_t)std::max<int64_t>(Gtot, 1), 0.0);
+  if (Gtot > 0)
+    HIP_TRY(c, hipMemcpyAsync(dth.data(), B.dtheta, sizeof(double) * Gtot, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, restore_snapshot(c, SF));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  st = check_error(c);
+  if (st != ITPP_OK) return st;
+  const int G = (int)c->glist.size();
+  std::vector<HostSum> da(c->terms.size());
+  HostSum dd;
+  for (int64_t g = 0; g < Gtot; ++g) {
+    const int sg = c->glist[(int)(g % G)];
+    const int k = c->sched_term[sg];
+    const double mlt = c->sched_mult[sg];
+    da[k].add(mlt * c->fwd_dtau * dth[g]);
+    dd.add(c->terms[k].alpha * mlt * dth[g]);
+  }
+  for (size_t k = 0; k < da.size(); ++k) d_alpha[k] = da[k].value();
+  *d_dtau = dd.value();
+  if (d_theta)
+    for (int64_t g = 0; g < Gtot; ++g) d_theta[g] = dth[g];
+  return ITPP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+itpp_status itpp_set_adjoint(itpp_ctx c, int32_t every_steps, int64_t workspace_bytes) {
+  if (!c) return ITPP_ERR_ARG;
+  if (every_steps < 0 || workspace_bytes < 0) return fail(c, ITPP_ERR_ARG, "negative argument");
+  if (every_steps > 0 && c->f32) return fail(c, ITPP_ERR_ARG, "the reverse sweep needs ITPP_F64 coefficients");
+  c->ckpt_every = every_steps;
+  c->adj_workspace = workspace_bytes;
+  free_ckpts(c);
+  c->fwd_valid = c->fwd_gates == 0;
+  return ITPP_OK;
+}
+
+itpp_status itpp_backward(itpp_ctx c, int32_t m, const uint64_t* x, const uint64_t* z, const double* coef,
+                          double* value, double* d_alpha, double* d_dtau, double* d_theta) {
+  if (!c) return ITPP_ERR_ARG;
+  if (!value || !d_alpha || !d_dtau) return fail(c, ITPP_ERR_ARG, "null output");
+  if (m < 0 || (m > 0 && (!x || !z || !coef))) return fail(c, ITPP_ERR_ARG, "bad observable arrays");
+  if (!c->ready) return fail(c, ITPP_ERR_STATE, "no valid state (reset required)");
+  if (c->f32) return fail(c, ITPP_ERR_ARG, "the reverse sweep needs ITPP_F64 coefficients");
+  if (c->ckpt_every <= 0 || !c->fwd_valid || (c->ckpts.empty() && c->fwd_gates > 0))
+    return fail(c, ITPP_ERR_STATE, "no replayable forward run: call itpp_set_adjoint, reset, then evolve with one dtau");
+  const int W = c->W;
+  for (int j = 0; j < m; ++j)
+    for (int q = 0; q < W; ++q) {
+      const int hi = c->n - 64 * q;
+      if (hi < 64) {
+        const uint64_t bad = hi <= 0 ? ~0ull : ~((1ull << hi) - 1ull);
+        if ((x[(size_t)j * W + q] | z[(size_t)j * W + q]) & bad)
+          return fail(c, ITPP_ERR_ARG, "observable has bits at or above n_qubits");
+      }
+    }
+  itpp_status st = check_error(c);
+  if (st != ITPP_OK) return st;
+  const bool timing = c->timing;
+  c->timing = false;
+  const int64_t Gtot = c->fwd_gates;
+  std::vector<void*> mem;
+  auto take = [&](uint64_t bytes) -> void* {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<uint64_t>(bytes, 256)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    mem.push_back(p);
+    return p;
+  };
+  AdjBuffers B{};
+  B.lam[0] = static_cast<double*>(take(c->cap * sizeof(double)));
+  B.lam[1] = static_cast<double*>(take(c->cap * sizeof(double)));
+  B.sdev = static_cast<double*>(take(2 * sizeof(double)));
+  B.part = static_cast<double*>(take(4 * c->status_cap * sizeof(double)));
+  B.ntiles = static_cast<uint64_t*>(take(sizeof(uint64_t)));
+  B.dtheta = static_cast<double*>(take(std::max<int64_t>(Gtot, 1) * sizeof(double)));
+  uint64_t* dx = static_cast<uint64_t*>(take(sizeof(uint64_t) * std::max(m, 1) * W));
+  uint64_t* dz = static_cast<uint64_t*>(take(sizeof(uint64_t) * std::max(m, 1) * W));
+  double* dc = static_cast<double*>(take(sizeof(double) * std::max(m, 1)));
+  Arena ar;
+  bool ok = B.lam[0] && B.lam[1] && B.sdev && B.part && B.ntiles && B.dtheta && dx && dz && dc;
+  if (ok) {
+    uint64_t want = (uint64_t)c->adj_workspace;
+    if (want == 0) {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess) want = (uint64_t)(0.7 * (double)fr);
+    }
+    ar.base = static_cast<uint8_t*>(take(want));
+    ar.size = want;
+    ok = ar.base != nullptr;
+  }
+  if (ok && m > 0) {
+    ok = hipMemcpyAsync(dx, x, sizeof(uint64_t) * m * W, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+         hipMemcpyAsync(dz, z, sizeof(uint64_t) * m * W, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+         hipMemcpyAsync(dc, coef, sizeof(double) * m, hipMemcpyHostToDevice, c->stream) == hipSuccess;
+  }
+  if (ok) {
+    double v = 0.0;
+    st = backward_impl(c, m, dx, dz, dc, &v, d_alpha, d_dtau, d_theta, ar, B);
+    if (st == ITPP_OK) *value = v;
+  } else {
+    st = fail(c, ITPP_ERR_OOM, "device memory for the reverse sweep is not available");
+  }
+  (void)hipStreamSynchronize(c->stream);
+  for (void* p : mem) (void)hipFree(p);
+  c->timing = timing;
+  if (st != ITPP_OK) c->ready = false;
+  return st;
 }
 
 }  // extern "C"

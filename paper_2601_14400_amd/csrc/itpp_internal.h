@@ -148,6 +148,18 @@ struct GateParams {
   uint8_t pos_in[kMaxBits];  // canonical bit -> rep position of the stored (input) keys
 };
 
+// Reverse-sweep arguments of the adjoint gate kernel (FP64 states only).
+struct AdjArgs {
+  const double* lam_out;    // lambda' = dL/da', parallel to the packed output of the gate
+  double* lam_in;           // lambda = dL/da for the gate's input (same positions as the input)
+  const Plan* plan_next;    // packed plan of the output
+  const Filter* filt_next;  // filter decided after the gate (its cI is b_I)
+  const double* s_in;       // sum of lambda' a' over the kept output
+  double* part;             // 4 doubles per tile: dtheta sum, compensation, sum lambda a, compensation
+  uint64_t* ntiles;         // tiles of the launch (written by the kernel)
+  uint64_t lam_out_len;     // elements of lam_out
+};
+
 // Selection scratch (device): candidates of the K-th value and tied keys.
 struct SelBuf {
   uint64_t* cand_bits;
@@ -167,6 +179,15 @@ hipError_t launch_select(int nw, int f32, Side out, const Plan* plan_out, const 
                          Filter* filt_out, Plan* plan_next, Ctl* ctl, SelBuf sel, const RepPos& rp,
                          int64_t K, int cap_fail, int spec, uint64_t serial, int grid, hipStream_t st);
 hipError_t launch_prepare(Plan* plan_out, Ctl* ctl, hipStream_t st);
+hipError_t launch_adjoint_gate(int nw, const GateParams& gp, Side in, const Plan* plan_in, Plan* plan_scratch,
+                               const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part,
+                               const AdjArgs& adj, int grid, hipStream_t st);
+hipError_t launch_adj_reduce(const double* part, const uint64_t* ntiles, double* dtheta_out, double* s_out,
+                             Ctl* ctl, hipStream_t st);
+hipError_t launch_pack(int nw, int f32, Side src, const Plan* plan_src, Side dst, Plan* plan_dst, int grid,
+                       hipStream_t st);
+hipError_t launch_seed(int nw, Side s, const Plan* plan, const Filter* filt, const RepPos& rp, const uint64_t* ox,
+                       const uint64_t* oz, const double* oc, int32_t m, double* lam, hipStream_t st);
 hipError_t launch_clear_status(TileStatus* status, uint64_t n, hipStream_t st);
 hipError_t launch_observe(int nw, int f32, Side s, const Plan* plan, const Filter* filt, const RepPos& rp,
                           const uint64_t* ox, const uint64_t* oz, const double* oc, int32_t m,

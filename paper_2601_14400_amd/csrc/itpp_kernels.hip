@@ -193,6 +193,14 @@ __device__ __forceinline__ T* coefs(const Side& s) {
   return static_cast<T*>(s.coef);
 }
 
+// Error-free sum (Knuth TwoSum): s + e == a + b exactly.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = __dadd_rn(a, b);
+  const double bb = __dsub_rn(s, a);
+  e = __dadd_rn(__dsub_rn(a, __dsub_rn(s, bb)), __dsub_rn(b, bb));
+}
+
+
 __device__ __forceinline__ int hist_bin(uint64_t bits) {
   const int64_t b = (int64_t)(bits >> kHistShift) - (int64_t)kHistBase;
   return b < 0 ? 0 : (b >= kHistBins ? kHistBins - 1 : (int)b);
@@ -495,14 +503,129 @@ __device__ __forceinline__ void values_from(T c, bool comm, bool paired, T cp, b
   }
 }
 
-template <int NW, int BLOCK, int TILE, typename T>
+// Reverse step (4) of one tile.  Element x survived the previous truncation
+// (info bit 0), commutes with Q (bit 1), has a surviving partner (bit 2),
+// and its self / branch output was written at a known position (bits 3 / 6).
+// lambda_u at an output position is lambda'[pos] / b_I, minus s / b_I at the
+// identity (the first element of the packed output), s = sum lambda' a'.
+template <int NW, int BLOCK, int TILE, typename T, typename Smem>
+__device__ void adjoint_tile(Smem& sm, const AdjArgs& adj, const GateParams& gp, const Filter& fin, T ch, T sh,
+                             uint64_t t, int nAt, int nt, uint64_t i0, uint64_t j0, const ClassView& VA,
+                             const ClassView& VB, int cA, int cB, Ctl* ctl) {
+  const int tid = threadIdx.x;
+  const double bI = adj.filt_next->cI;
+  const double s_out = *adj.s_in;
+  // pass 1: lambda_u at every element's self output, kept in the key array
+  for (int x = tid; x < nt; x += BLOCK) {
+    const uint16_t inf = sm.info[x];
+    double lu = 0.0;
+    if (inf & 8u) {
+      const bool isA = x < nAt;
+      const int es = (inf >> 4) & 3;
+      const int cls = isA ? cA : cB;
+      const uint64_t pos = sm.out_base[cls][es] + sm.excl[(isA ? 0 : 1) * kMaxClasses + es] + sm.rs[x];
+      if (pos >= region_end(sm.out_base, cls, es)) {
+        atomicMax(&ctl->error, kErrCapacity);
+      } else {
+        lu = adj.lam_out[pos] / bI;
+        if (pos == 0) lu = lu - s_out / bI;
+      }
+    }
+    sm.key[0][x] = (uint64_t)__double_as_longlong(lu);
+  }
+  __syncthreads();
+  // pass 2: lambda at the inputs, dL/dtheta and sum lambda a
+  double st = 0.0, ct = 0.0, ss = 0.0, cs = 0.0;
+  for (int x = tid; x < nt; x += BLOCK) {
+    const uint16_t inf = sm.info[x];
+    const bool isA = x < nAt;
+    const uint64_t p = isA ? phys_sel(VA, i0 + x) : phys_sel(VB, j0 + (x - nAt));
+    double li = 0.0;
+    if (inf & 1u) {
+      const double a = (double)sm.coef[x];
+      const double lu = __longlong_as_double((long long)sm.key[0][x]);
+      if (!(inf & 2u)) {
+        li = lu;
+      } else {
+        double lo = 0.0;
+        if (inf & 4u) {
+          lo = __longlong_as_double((long long)sm.key[0][sm.partner[x]]);
+        } else if (inf & 64u) {
+          const int eb = (inf >> 7) & 3;
+          const int cls = isA ? cB : cA;
+          const uint64_t pos = sm.out_base[cls][eb] + sm.excl[(isA ? 1 : 0) * kMaxClasses + eb] + sm.rb[x];
+          if (pos >= region_end(sm.out_base, cls, eb)) {
+            atomicMax(&ctl->error, kErrCapacity);
+          } else {
+            lo = adj.lam_out[pos] / bI;
+            if (pos == 0) lo = lo - s_out / bI;
+          }
+        }
+        const bool neg = (inf >> 9) & 1;  // Q P = -R
+        const double chd = (double)ch, shd = (double)sh;
+        const double t1 = __dmul_rn(chd, lu), t2 = __dmul_rn(shd, lo);
+        li = neg ? __dadd_rn(t1, t2) : __dsub_rn(t1, t2);
+        const double d1 = __dmul_rn(shd, lu), d2 = __dmul_rn(chd, lo);
+        const double dt = __dmul_rn(a, neg ? __dadd_rn(d1, d2) : __dsub_rn(d1, d2));
+        double sres, err;
+        two_sum(st, dt, sres, err);
+        st = sres;
+        ct = __dadd_rn(ct, err);
+      }
+      double sres, err;
+      two_sum(ss, __dmul_rn(li, a), sres, err);
+      ss = sres;
+      cs = __dadd_rn(cs, err);
+    }
+    adj.lam_in[p] = li;
+  }
+  // fixed-order block reduction of the two compensated sums (the key
+  // arrays are free again and hold 4 * BLOCK doubles)
+  static_assert(NW * (TILE + 2) >= 4 * BLOCK, "reduction scratch");
+  double* red = reinterpret_cast<double*>(&sm.key[0][0]);
+  __syncthreads();
+  red[tid] = st;
+  red[BLOCK + tid] = ct;
+  red[2 * BLOCK + tid] = ss;
+  red[3 * BLOCK + tid] = cs;
+  __syncthreads();
+  for (int h = BLOCK / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+      double sres, err;
+      two_sum(red[tid], red[tid + h], sres, err);
+      red[tid] = sres;
+      red[BLOCK + tid] = __dadd_rn(__dadd_rn(red[BLOCK + tid], red[BLOCK + tid + h]), err);
+      two_sum(red[2 * BLOCK + tid], red[2 * BLOCK + tid + h], sres, err);
+      red[2 * BLOCK + tid] = sres;
+      red[3 * BLOCK + tid] = __dadd_rn(__dadd_rn(red[3 * BLOCK + tid], red[3 * BLOCK + tid + h]), err);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    adj.part[4 * t + 0] = red[0];
+    adj.part[4 * t + 1] = red[BLOCK];
+    adj.part[4 * t + 2] = red[2 * BLOCK];
+    adj.part[4 * t + 3] = red[3 * BLOCK];
+  }
+  __syncthreads();
+}
+
+//
+// ADJ = true is the reverse sweep of the same gate (frozen support): the
+// load, walk, scan and look-back are those of the forward gate, so every
+// element finds the positions its outputs had in the forward run's packed
+// output; step (4) then gathers lambda' there and writes lambda for the input
+// (adjoint of Eq. ITPP_PropRules, of the kept-set restriction and of the
+// division by the identity coefficient), with per-tile partial sums of
+// dL/dtheta and of sum lambda a.
+template <int NW, int BLOCK, int TILE, typename T, bool ADJ>
 __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, Side out,
                                                       const Plan* __restrict__ plan_in,
                                                       Plan* __restrict__ plan_out,
                                                       const Filter* __restrict__ filt_in,
                                                       const uint64_t* __restrict__ part,
                                                       Ctl* __restrict__ ctl,
-                                                      TileStatus* __restrict__ status) {
+                                                      TileStatus* __restrict__ status, AdjArgs adj) {
   using Smem = GateSmem<NW, BLOCK, TILE, T>;
   constexpr int PER = Smem::PER;
   __shared__ Smem sm;
@@ -535,16 +658,28 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
   if (tid < kMaxClasses * kMaxClasses) sm.ncnt[tid] = 0;
   if (tid == 0) {
     const Plan* __restrict__ pin = plan_in;
-    // output region capacities: cap(c,e) = n[c][e] + n[~c][e ^ ov]
     uint64_t acc = 0;
-    for (int c = 0; c < kMaxClasses; ++c)
-      for (int e = 0; e < kMaxClasses; ++e) {
-        sm.out_base[c][e] = acc;
-        if (c < ncls && e < ncls1) acc += (uint64_t)pin->ncnt[c][e] + (uint64_t)pin->ncnt[c ^ full][e ^ gp.ov];
-      }
+    if constexpr (ADJ) {
+      // the forward output, packed: region (c, e) holds exactly cnt[c][e]
+      const Plan* __restrict__ pn = adj.plan_next;
+      for (int c = 0; c < kMaxClasses; ++c)
+        for (int e = 0; e < kMaxClasses; ++e) {
+          sm.out_base[c][e] = acc;
+          if (c < ncls && e < ncls1) acc += pn->cnt[c][e];
+        }
+      if (pn->base[0][0] != 0 || acc > adj.lam_out_len) atomicMax(&ctl->error, kErrCapacity);
+      if (blockIdx.x == 0) *adj.ntiles = 0;
+    } else {
+      // output region capacities: cap(c,e) = n[c][e] + n[~c][e ^ ov]
+      for (int c = 0; c < kMaxClasses; ++c)
+        for (int e = 0; e < kMaxClasses; ++e) {
+          sm.out_base[c][e] = acc;
+          if (c < ncls && e < ncls1) acc += (uint64_t)pin->ncnt[c][e] + (uint64_t)pin->ncnt[c ^ full][e ^ gp.ov];
+        }
+    }
     for (int e = 0; e < kMaxClasses; ++e) sm.out_base[kMaxClasses][e] = acc;
     if (acc > gp.cap_elems) atomicMax(&ctl->error, kErrCapacity);
-    if (blockIdx.x == 0) {
+    if (blockIdx.x == 0 && !ADJ) {
       for (int c = 0; c < kMaxClasses; ++c)
         for (int e = 0; e < kMaxClasses; ++e) plan_out->base[c][e] = sm.out_base[c][e];
       plan_out->wc = w;
@@ -556,6 +691,9 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
   }
   __syncthreads();
   const uint64_t total_tiles = sm.L.tiles_before[sm.L.njoin];
+  if constexpr (ADJ) {
+    if (blockIdx.x == 0 && tid == 0) *adj.ntiles = total_tiles;
+  }
   if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kErrNone || ctl->halt) return;
 
   for (;;) {
@@ -866,7 +1004,7 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
 #pragma unroll
         for (int q = 0; q < 2 * kMaxClasses; ++q) sm.excl[q] = excl[q];
         // the last tile of the join publishes the region fill counts
-        if (t + 1 == sm.L.tiles_before[j + 1]) {
+        if (!ADJ && t + 1 == sm.L.tiles_before[j + 1]) {
 #pragma unroll
           for (int e = 0; e < kMaxClasses; ++e) {
             if (e < ncls1) {
@@ -878,6 +1016,10 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
       }
     }
     __syncthreads();
+    if constexpr (ADJ) {
+      adjoint_tile<NW, BLOCK, TILE, T>(sm, adj, gp, fin, ch, sh, t, nAt, nt, i0, j0, VA, VB, cA, cB, ctl);
+      continue;
+    }
     // (4) write outputs
     uint32_t written = 0, above = 0;
     for (int x = tid; x < nt; x += BLOCK) {
@@ -946,6 +1088,7 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
   }
   // flush per-workgroup statistics
   __syncthreads();
+  if constexpr (ADJ) return;
   if (win_hi > win_lo)
     for (int i = tid; i < kFineBins; i += BLOCK) {
       const uint32_t v = sm.fhist[i];
@@ -1352,11 +1495,6 @@ __global__ __launch_bounds__(1024) void select_exact(Side out, Filter* filt_out,
 // <O> = sum_j o_j a_{P_j}: binary search of every observable string in its
 // class regions, filter and normalise, compensated (TwoSum) reduction in a
 // fixed order.
-__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
-  s = __dadd_rn(a, b);
-  const double bb = __dsub_rn(s, a);
-  e = __dadd_rn(__dsub_rn(a, __dsub_rn(s, bb)), __dsub_rn(b, bb));
-}
 
 template <int NW, typename T>
 __global__ __launch_bounds__(256) void observe_kernel(Side s, const Plan* plan, const Filter* filt,
@@ -1442,6 +1580,119 @@ __global__ void export_kernel(Side s, const Plan* plan, const Filter* filt, RepP
 }
 
 // ---------------------------------------------------------------------------
+// Reverse sweep support.
+
+// Copy a stored state into a packed layout: region (c, e) at the running sum
+// of the counts of the regions before it (c major, e minor), so the state
+// occupies exactly as many elements as it holds.
+template <int NW, typename T>
+__global__ void pack_kernel(Side src, const Plan* __restrict__ plan_src, Side dst, Plan* __restrict__ plan_dst) {
+  const Plan p = *plan_src;
+  const int nc = 1 << p.wc, ne = 1 << p.we;
+  uint64_t nb[kMaxClasses][kMaxClasses];
+  uint64_t acc = 0;
+  for (int c = 0; c < kMaxClasses; ++c)
+    for (int e = 0; e < kMaxClasses; ++e) {
+      nb[c][e] = acc;
+      if (c < nc && e < ne) acc += p.cnt[c][e];
+    }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Plan q = p;
+    for (int c = 0; c < kMaxClasses; ++c)
+      for (int e = 0; e < kMaxClasses; ++e) q.base[c][e] = nb[c][e];
+    *plan_dst = q;
+  }
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (int c = 0; c < nc; ++c)
+    for (int e = 0; e < ne; ++e) {
+      const uint64_t sb = p.base[c][e], db = nb[c][e], cnt = p.cnt[c][e];
+      for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
+#pragma unroll
+        for (int q = 0; q < NW; ++q) dst.kw[q][db + i] = src.kw[q][sb + i];
+        coefs<T>(dst)[db + i] = coefs<T>(src)[sb + i];
+      }
+    }
+}
+
+// lambda = dL/da for L = sum_j o_j a[P_j]: o_j at the position of every
+// observable string the state holds (and keeps), zero elsewhere.
+template <int NW>
+__global__ __launch_bounds__(256) void seed_kernel(Side s, const Plan* plan, const Filter* filt, RepPos rp,
+                                                   const uint64_t* ox, const uint64_t* oz, const double* oc,
+                                                   int32_t m, double* lam) {
+  const Plan& p = *plan;
+  const Filter f = *filt;
+  constexpr int W = NW / 2;
+  const int n = rp.nbits / 2;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
+    Key<NW> k;
+    for (int q = 0; q < NW; ++q) k.w[q] = 0;
+    for (int qb = 0; qb < n; ++qb) {
+      if ((ox[(size_t)j * W + (qb >> 6)] >> (qb & 63)) & 1ull) xor_bit(k, rp.pos[qb], 1ull);
+      if ((oz[(size_t)j * W + (qb >> 6)] >> (qb & 63)) & 1ull) xor_bit(k, rp.pos[n + qb], 1ull);
+    }
+    const int e = class_of(k, rp.nbits, p.we);
+    for (int c = 0; c < (1 << p.wc); ++c) {
+      uint64_t lo = p.base[c][e], hi = p.base[c][e] + p.cnt[c][e];
+      while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (key_less(load_key<NW>(s, mid), k))
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      if (lo < p.base[c][e] + p.cnt[c][e] && key_eq(load_key<NW>(s, lo), k)) {
+        if (survives(k, coefs<double>(s)[lo], f, rp.pos, rp.nbits)) atomicAdd(&lam[lo], oc[j]);
+      }
+    }
+  }
+}
+
+// dL/dtheta of the gate and sum lambda a of its input, from the per-tile
+// partials in tile order (compensated); the ticket is rearmed.
+__global__ __launch_bounds__(256) void adj_reduce_kernel(const double* part, const uint64_t* ntiles,
+                                                         double* dtheta_out, double* s_out, Ctl* ctl) {
+  __shared__ double r[4][256];
+  const int tid = threadIdx.x;
+  const uint64_t nt = *ntiles;
+  const uint64_t per = (nt + 255) / 256;
+  double st = 0.0, ct = 0.0, ss = 0.0, cs = 0.0;
+  for (uint64_t q = 0; q < per; ++q) {
+    const uint64_t t = (uint64_t)tid * per + q;
+    if (t >= nt) break;
+    double sres, err;
+    two_sum(st, part[4 * t], sres, err);
+    st = sres;
+    ct = __dadd_rn(__dadd_rn(ct, err), part[4 * t + 1]);
+    two_sum(ss, part[4 * t + 2], sres, err);
+    ss = sres;
+    cs = __dadd_rn(__dadd_rn(cs, err), part[4 * t + 3]);
+  }
+  r[0][tid] = st;
+  r[1][tid] = ct;
+  r[2][tid] = ss;
+  r[3][tid] = cs;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+      double sres, err;
+      two_sum(r[0][tid], r[0][tid + h], sres, err);
+      r[0][tid] = sres;
+      r[1][tid] = __dadd_rn(__dadd_rn(r[1][tid], r[1][tid + h]), err);
+      two_sum(r[2][tid], r[2][tid + h], sres, err);
+      r[2][tid] = sres;
+      r[3][tid] = __dadd_rn(__dadd_rn(r[3][tid], r[3][tid + h]), err);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    *dtheta_out = __dadd_rn(r[0][0], r[1][0]);
+    *s_out = __dadd_rn(r[2][0], r[3][0]);
+    ctl->ticket = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers.
 #ifndef ITPP_GATE_BLOCK
 #define ITPP_GATE_BLOCK 1024
@@ -1512,10 +1763,48 @@ hipError_t launch_partition(int nw, const GateParams& gp, Side in, const Plan* p
 hipError_t launch_gate(int nw, int f32, const GateParams& gp, Side in, Side out, const Plan* plan_in,
                        Plan* plan_out, const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part,
                        int grid, hipStream_t st) {
+  const AdjArgs none{};
   ITPP_DISPATCH(nw, f32,
-                hipLaunchKernelGGL((gate_kernel<NWC, kBlock, TileFor<NWC>::value, TC>), dim3(grid), dim3(kBlock),
-                                   0, st, gp, in, out, plan_in, plan_out, filt_in, (const uint64_t*)part, ctl,
-                                   status));
+                hipLaunchKernelGGL((gate_kernel<NWC, kBlock, TileFor<NWC>::value, TC, false>), dim3(grid),
+                                   dim3(kBlock), 0, st, gp, in, out, plan_in, plan_out, filt_in,
+                                   (const uint64_t*)part, ctl, status, none));
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_gate(int nw, const GateParams& gp, Side in, const Plan* plan_in, Plan* plan_scratch,
+                               const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part,
+                               const AdjArgs& adj, int grid, hipStream_t st) {
+  const Side none{};
+  if (nw == 2)
+    hipLaunchKernelGGL((gate_kernel<2, kBlock, TileFor<2>::value, double, true>), dim3(grid), dim3(kBlock), 0, st,
+                       gp, in, none, plan_in, plan_scratch, filt_in, (const uint64_t*)part, ctl, status, adj);
+  else
+    hipLaunchKernelGGL((gate_kernel<4, kBlock, TileFor<4>::value, double, true>), dim3(grid), dim3(kBlock), 0, st,
+                       gp, in, none, plan_in, plan_scratch, filt_in, (const uint64_t*)part, ctl, status, adj);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_reduce(const double* part, const uint64_t* ntiles, double* dtheta_out, double* s_out,
+                             Ctl* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(adj_reduce_kernel, dim3(1), dim3(256), 0, st, part, ntiles, dtheta_out, s_out, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(int nw, int f32, Side src, const Plan* plan_src, Side dst, Plan* plan_dst, int grid,
+                       hipStream_t st) {
+  ITPP_DISPATCH(nw, f32,
+                hipLaunchKernelGGL((pack_kernel<NWC, TC>), dim3(grid), dim3(256), 0, st, src, plan_src, dst,
+                                   plan_dst));
+  return hipGetLastError();
+}
+
+hipError_t launch_seed(int nw, Side s, const Plan* plan, const Filter* filt, const RepPos& rp, const uint64_t* ox,
+                       const uint64_t* oz, const double* oc, int32_t m, double* lam, hipStream_t st) {
+  const int grid = (m + 255) / 256 > 0 ? (m + 255) / 256 : 1;
+  if (nw == 2)
+    hipLaunchKernelGGL(seed_kernel<2>, dim3(grid), dim3(256), 0, st, s, plan, filt, rp, ox, oz, oc, m, lam);
+  else
+    hipLaunchKernelGGL(seed_kernel<4>, dim3(grid), dim3(256), 0, st, s, plan, filt, rp, ox, oz, oc, m, lam);
   return hipGetLastError();
 }
 
