@@ -198,8 +198,12 @@ itpp_status itpp_backward(itpp_ctx ctx, int32_t n_strings, const uint64_t* x, co
  *    the strings above a margin below the K-th value predicted from the
  *    previous gate; if fewer than K-1 strings pass, the gate is redone
  *    without the margin, so the kept set is always the exact one.
- *  ITPP_OPT_SPEC_MARGIN (default 0.9): that margin as a factor in (0, 1]. */
-typedef enum { ITPP_OPT_SPECULATION = 1, ITPP_OPT_SPEC_MARGIN = 2 } itpp_option;
+ *  ITPP_OPT_SPEC_MARGIN (default 0.9): that margin as a factor in (0, 1].
+ *  ITPP_OPT_GATE_SHAPE (default 0): 0 = one 1024-thread workgroup per CU
+ *    with 4000 (n <= 64) or 2000 (n <= 128) strings per tile; 1 = two
+ *    512-thread workgroups per CU with 2000 or 1500 strings per tile (more
+ *    tiles in flight, better for small states). */
+typedef enum { ITPP_OPT_SPECULATION = 1, ITPP_OPT_SPEC_MARGIN = 2, ITPP_OPT_GATE_SHAPE = 3 } itpp_option;
 itpp_status itpp_set_option(itpp_ctx ctx, int32_t option, double value);
 
 /* Enable (1) or disable (0) per-gate HIP event timing; enabling clears the
@@ -208,6 +212,42 @@ itpp_status itpp_set_timing(itpp_ctx ctx, int32_t enable);
 
 /* Wait for the stream and return the accumulated timing. */
 itpp_status itpp_get_timing(itpp_ctx ctx, itpp_timing* out);
+
+/* Batches of independent instances (the same method on many Hamiltonians,
+ * steps and sizes at once).  itpp_batch_create makes n_inst contexts from
+ * cfgs[i] (each cfg as for itpp_create; its stream field is ignored: every
+ * instance gets a stream of its own) whose device buffers are consecutive
+ * slices of one allocation sized to the sum of their needs.  The instances
+ * are ordinary contexts: itpp_batch_instance returns instance i (owned by
+ * the batch; do not destroy it) for set_hamiltonian, set_schedule,
+ * set_option, expect, export, ...  Every instance computes exactly what a
+ * single context with the same configuration computes.
+ * ITPP_ERR_ARG for n_inst < 1 or a bad configuration, ITPP_ERR_OOM if the
+ * arena cannot be allocated. */
+typedef struct itpp_batch_s* itpp_batch;
+itpp_status itpp_batch_create(int32_t n_inst, const itpp_config* cfgs, itpp_batch* out);
+itpp_status itpp_batch_destroy(itpp_batch b);
+itpp_ctx itpp_batch_instance(itpp_batch b, int32_t i);
+
+/* Host worker threads that drive the instances' streams (1..64, default 4). */
+itpp_status itpp_batch_set_workers(itpp_batch b, int32_t workers);
+
+/* Evolve instance i by n_steps[i] Trotter steps of dtau[i] (as itpp_evolve),
+ * all instances concurrently; st (NULL or n_inst entries) receives each
+ * instance's statistics.  Returns the first instance error (message from
+ * itpp_batch_last_error). */
+itpp_status itpp_batch_evolve(itpp_batch b, const double* dtau, const int64_t* n_steps, itpp_stats* st);
+
+/* Autotuner: for every gate kernel shape (ITPP_OPT_GATE_SHAPE 0, 1) and
+ * 1, 2, 4, 8 workers, reset all instances, apply warm_gates gates untimed,
+ * then time probe_gates more gates on every instance; keep the combination
+ * with the most term updates per second (written to the non-NULL outputs).
+ * Leaves every instance reset with the chosen shape. */
+itpp_status itpp_batch_autotune(itpp_batch b, const double* dtau, int64_t warm_gates, int64_t probe_gates,
+                                int32_t* best_shape, int32_t* best_workers, double* best_rate);
+
+/* Message for the last batch error (b == NULL: last creation failure). */
+const char* itpp_batch_last_error(itpp_batch b);
 
 /* Message for the last error on ctx (for ctx == NULL: the last itpp_create
  * failure of this thread). */

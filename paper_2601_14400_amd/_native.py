@@ -23,6 +23,8 @@ STATUS = {0: "ITPP_OK", 1: "ITPP_ERR_ARG", 2: "ITPP_ERR_OOM", 3: "ITPP_ERR_CAP",
 EXPORTED = ["itpp_create", "itpp_destroy", "itpp_set_hamiltonian", "itpp_set_schedule",
             "itpp_reset", "itpp_evolve", "itpp_evolve_gates", "itpp_expect", "itpp_num_terms", "itpp_export",
             "itpp_set_adjoint", "itpp_backward", "itpp_set_option", "itpp_set_timing", "itpp_get_timing",
+            "itpp_batch_create", "itpp_batch_destroy", "itpp_batch_instance", "itpp_batch_set_workers",
+            "itpp_batch_evolve", "itpp_batch_autotune", "itpp_batch_last_error",
             "itpp_last_error", "itpp_version"]
 
 
@@ -87,12 +89,22 @@ def load_library(path: Optional[str] = None):
     lib.itpp_set_option.argtypes = [vp, i32, dbl]
     lib.itpp_set_timing.argtypes = [vp, i32]
     lib.itpp_get_timing.argtypes = [vp, ctypes.POINTER(ItppTiming)]
+    lib.itpp_batch_create.argtypes = [i32, ctypes.POINTER(ItppConfig), ctypes.POINTER(vp)]
+    lib.itpp_batch_destroy.argtypes = [vp]
+    lib.itpp_batch_instance.argtypes = [vp, i32]
+    lib.itpp_batch_set_workers.argtypes = [vp, i32]
+    lib.itpp_batch_evolve.argtypes = [vp, vp, vp, vp]
+    lib.itpp_batch_autotune.argtypes = [vp, vp, i64, i64, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                        ctypes.POINTER(dbl)]
+    lib.itpp_batch_last_error.argtypes = [vp]
+    lib.itpp_batch_last_error.restype = ctypes.c_char_p
     lib.itpp_last_error.argtypes = [vp]
     lib.itpp_last_error.restype = ctypes.c_char_p
     lib.itpp_version.restype = ctypes.c_char_p
     for name in EXPORTED:
-        if name not in ("itpp_last_error", "itpp_version"):
+        if name not in ("itpp_last_error", "itpp_version", "itpp_batch_last_error", "itpp_batch_instance"):
             getattr(lib, name).restype = ctypes.c_int
+    lib.itpp_batch_instance.restype = vp
     if path is None:
         _lib = lib
     return lib
@@ -172,9 +184,23 @@ class Engine:
             msg = self._lib.itpp_last_error(self._h)
             raise ItppError(rc, msg.decode() if msg else "")
 
+    @classmethod
+    def _borrowed(cls, lib, handle, n_qubits: int):
+        """An Engine view of a context owned by a Batch (not destroyed here)."""
+        e = cls.__new__(cls)
+        e._lib = lib
+        e.n = int(n_qubits)
+        e.W = (e.n + 63) // 64
+        e.n_terms = 0
+        e.gates_since_reset = 0
+        e._h = handle
+        e._owned = False
+        return e
+
     def close(self):
         if getattr(self, "_h", None):
-            self._lib.itpp_destroy(self._h)
+            if getattr(self, "_owned", True):
+                self._lib.itpp_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -241,7 +267,7 @@ class Engine:
                 "spec_gates": st.spec_gates, "spec_retries": st.spec_retries}
 
     def set_option(self, name: str, value: float):
-        opt = {"speculation": 1, "spec_margin": 2}[name]
+        opt = {"speculation": 1, "spec_margin": 2, "gate_shape": 3}[name]
         self._check(self._lib.itpp_set_option(self._h, opt, float(value)))
 
     def set_timing(self, enable: bool = True):
@@ -284,3 +310,72 @@ class Engine:
 
 def version() -> str:
     return load_library().itpp_version().decode()
+
+
+class Batch:
+    """Independent instances in one device arena, evolved concurrently
+    (see itpp_batch_* in include/itpp.h).  ``instances[i]`` is an Engine
+    view of instance i for the single-instance calls."""
+
+    def __init__(self, configs: Sequence[Dict]):
+        self._lib = load_library()
+        n = len(configs)
+        arr = (ItppConfig * n)()
+        for i, c in enumerate(configs):
+            arr[i].n_qubits = int(c["n_qubits"])
+            arr[i].precision = {"f64": 0, "f32": 1}[c.get("precision", "f64")]
+            arr[i].threshold = float(c["threshold"])
+            arr[i].max_terms = int(c["max_terms"])
+            arr[i].cap_policy = {"topk": 0, "fail": 1}[c.get("cap_policy", "topk")]
+            arr[i].stream = None
+            arr[i].device_bytes_limit = int(c.get("device_bytes_limit", 0))
+        h = ctypes.c_void_p()
+        rc = self._lib.itpp_batch_create(n, arr, ctypes.byref(h))
+        if rc != 0:
+            msg = self._lib.itpp_batch_last_error(None)
+            raise ItppError(rc, "itpp_batch_create: " + (msg.decode() if msg else ""))
+        self._h = h
+        self.instances = [Engine._borrowed(self._lib, ctypes.c_void_p(self._lib.itpp_batch_instance(h, i)),
+                                           configs[i]["n_qubits"]) for i in range(n)]
+
+    def _check(self, rc: int):
+        if rc != 0:
+            msg = self._lib.itpp_batch_last_error(self._h)
+            raise ItppError(rc, msg.decode() if msg else "")
+
+    def set_workers(self, workers: int):
+        self._check(self._lib.itpp_batch_set_workers(self._h, int(workers)))
+
+    def evolve(self, dtaus: Sequence[float], n_steps: Sequence[int]) -> List[Dict[str, float]]:
+        n = len(self.instances)
+        d = np.ascontiguousarray(dtaus, dtype=np.float64)
+        k = np.ascontiguousarray(n_steps, dtype=np.int64)
+        st = (ItppStats * n)()
+        self._check(self._lib.itpp_batch_evolve(self._h, d.ctypes.data, k.ctypes.data, st))
+        out = []
+        for i in range(n):
+            self.instances[i].gates_since_reset += st[i].n_gates
+            out.append(Engine._stats(st[i]))
+        return out
+
+    def autotune(self, dtaus: Sequence[float], warm_gates: int, probe_gates: int) -> Tuple[int, int, float]:
+        d = np.ascontiguousarray(dtaus, dtype=np.float64)
+        sh, wk, rate = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        self._check(self._lib.itpp_batch_autotune(self._h, d.ctypes.data, int(warm_gates), int(probe_gates),
+                                                  ctypes.byref(sh), ctypes.byref(wk), ctypes.byref(rate)))
+        for e in self.instances:
+            e.gates_since_reset = 0
+        return int(sh.value), int(wk.value), float(rate.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for e in self.instances:
+                e._h = None
+            self._lib.itpp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

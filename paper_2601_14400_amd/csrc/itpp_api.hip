@@ -9,11 +9,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/itpp.h"
@@ -54,6 +57,12 @@ struct itpp_ctx_s {
   itpp_config cfg{};
   int n = 0, W = 1, NW = 2, nbits = 2;
   int f32 = 0, coef_bytes = 8;  // stored coefficient type: binary32 or binary64
+  int shape = 0;                // gate kernel shape (see gate_tile)
+  // device memory: own allocations, or a slice of a batch arena
+  uint8_t* arena = nullptr;
+  uint64_t arena_size = 0, arena_top = 0;
+  bool measure = false;          // only add up the bytes the buffers need
+  hipStream_t own_stream = nullptr;
   hipStream_t stream = nullptr;
   int device = 0;
   int cus = 256;
@@ -184,6 +193,18 @@ hipError_t drain_events(itpp_ctx c) {
 
 template <typename T>
 hipError_t dalloc(itpp_ctx c, T** p, size_t count) {
+  const uint64_t bytes = ((std::max<size_t>(count, 1) * sizeof(T)) + 255) & ~(uint64_t)255;
+  if (c->measure) {
+    c->arena_top += bytes;
+    *p = nullptr;
+    return hipSuccess;
+  }
+  if (c->arena) {
+    if (c->arena_top + bytes > c->arena_size) return hipErrorOutOfMemory;
+    *p = reinterpret_cast<T*>(c->arena + c->arena_top);
+    c->arena_top += bytes;
+    return hipSuccess;
+  }
   void* q = nullptr;
   hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
   if (e == hipSuccess) {
@@ -325,8 +346,11 @@ const char* itpp_last_error(itpp_ctx ctx) {
   return ctx->err.c_str();
 }
 
-itpp_status itpp_create(const itpp_config* cfg, itpp_ctx* out) {
-  if (!cfg || !out) return create_fail(ITPP_ERR_ARG, "null argument");
+}  // extern "C"
+
+namespace {
+
+itpp_status check_config(const itpp_config* cfg) {
   if (cfg->n_qubits < 1 || cfg->n_qubits > 64 * kMaxWords)
     return create_fail(ITPP_ERR_ARG, "n_qubits must be in 1..128");
   if (!(cfg->threshold >= 0.0) || !std::isfinite(cfg->threshold) || cfg->threshold >= 1.0)
@@ -336,16 +360,24 @@ itpp_status itpp_create(const itpp_config* cfg, itpp_ctx* out) {
     return create_fail(ITPP_ERR_ARG, "precision must be ITPP_F64 or ITPP_F32");
   if (cfg->cap_policy != ITPP_CAP_TOPK && cfg->cap_policy != ITPP_CAP_FAIL)
     return create_fail(ITPP_ERR_ARG, "unknown cap policy");
-  int dev = 0;
-  hipError_t he = hipGetDevice(&dev);
+  return ITPP_OK;
+}
+
+itpp_status device_props(int* dev, hipDeviceProp_t* prop) {
+  hipError_t he = hipGetDevice(dev);
   if (he != hipSuccess) return create_fail(ITPP_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(he));
-  hipDeviceProp_t prop;
-  he = hipGetDeviceProperties(&prop, dev);
+  he = hipGetDeviceProperties(prop, *dev);
   if (he != hipSuccess)
     return create_fail(ITPP_ERR_DEVICE, std::string("hipGetDeviceProperties: ") + hipGetErrorString(he));
-  if (std::string(prop.gcnArchName).rfind("gfx950", 0) != 0)
-    return create_fail(ITPP_ERR_DEVICE, std::string("device is ") + prop.gcnArchName + ", not gfx950");
+  if (std::string(prop->gcnArchName).rfind("gfx950", 0) != 0)
+    return create_fail(ITPP_ERR_DEVICE, std::string("device is ") + prop->gcnArchName + ", not gfx950");
+  return ITPP_OK;
+}
 
+// Create a context.  arena != NULL: its buffers are carved from
+// [arena, arena + arena_size); measured != NULL: only return the bytes needed.
+itpp_status create_impl(const itpp_config* cfg, int dev, const hipDeviceProp_t& prop, uint8_t* arena,
+                        uint64_t arena_size, uint64_t* measured, itpp_ctx* out) {
   itpp_ctx c = new (std::nothrow) itpp_ctx_s;
   if (!c) return ITPP_ERR_OOM;
   c->cfg = *cfg;
@@ -358,13 +390,16 @@ itpp_status itpp_create(const itpp_config* cfg, itpp_ctx* out) {
   c->stream = static_cast<hipStream_t>(cfg->stream);
   c->device = dev;
   c->cus = prop.multiProcessorCount;
+  c->arena = arena;
+  c->arena_size = arena_size;
+  c->measure = measured != nullptr;
   // every stored string comes from at most two outputs of a survivor and the
   // next gate's regions reserve twice the stored count: 4 K elements per side
   uint64_t kmax = (uint64_t)cfg->max_terms;
   if (c->n <= 30) kmax = std::min<uint64_t>(kmax, 1ull << (2 * c->n));
   c->cap = 4 * kmax + 64;
   const uint64_t elem_bytes = (uint64_t)c->NW * 8 + (uint64_t)c->coef_bytes;
-  const int tile = gate_tile(c->NW);
+  const int tile = gate_min_tile(c->NW);
   c->status_cap = c->cap / (uint64_t)tile + 16;
   const uint64_t sel_cap = 2 * kmax + 64;
   const uint64_t bytes = 2 * c->cap * elem_bytes + c->status_cap * kStatusWords * sizeof(TileStatus) +
@@ -391,14 +426,19 @@ itpp_status itpp_create(const itpp_config* cfg, itpp_ctx* out) {
   if (ok) ok = dalloc(c, &c->sel.cand_idx, sel_cap) == hipSuccess;
   if (ok) ok = dalloc(c, &c->sel.tie_keys, sel_cap * c->NW) == hipSuccess;
   if (ok) ok = dalloc(c, &c->d_result, 4) == hipSuccess;
+  if (measured) {
+    *measured = c->arena_top;
+    delete c;
+    return ITPP_OK;
+  }
   if (!ok) {
     (void)hipGetLastError();
     free_all(c);
     delete c;
-    return create_fail(ITPP_ERR_OOM, "hipMalloc of the state buffers failed");
+    return create_fail(ITPP_ERR_OOM, "device memory for the state buffers is not available");
   }
   c->sel.cap = sel_cap;
-  he = hipMemsetAsync(c->status, 0, c->status_cap * kStatusWords * sizeof(TileStatus), c->stream);
+  hipError_t he = hipMemsetAsync(c->status, 0, c->status_cap * kStatusWords * sizeof(TileStatus), c->stream);
   if (he == hipSuccess) he = hipMemsetAsync(c->plan, 0, 2 * sizeof(Plan), c->stream);
   if (he != hipSuccess) {
     free_all(c);
@@ -415,11 +455,27 @@ itpp_status itpp_create(const itpp_config* cfg, itpp_ctx* out) {
   return ITPP_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+itpp_status itpp_create(const itpp_config* cfg, itpp_ctx* out) {
+  if (!cfg || !out) return create_fail(ITPP_ERR_ARG, "null argument");
+  itpp_status s = check_config(cfg);
+  if (s != ITPP_OK) return s;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  s = device_props(&dev, &prop);
+  if (s != ITPP_OK) return s;
+  return create_impl(cfg, dev, prop, nullptr, 0, nullptr, out);
+}
+
 itpp_status itpp_destroy(itpp_ctx ctx) {
   if (!ctx) return ITPP_OK;
   (void)hipStreamSynchronize(ctx->stream);
   free_ckpts(ctx);
   free_all(ctx);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
   delete ctx;
   return ITPP_OK;
 }
@@ -516,7 +572,7 @@ itpp_status itpp_evolve_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_sta
 
 // Parameters of gate i of the schedule's gate list for a state in rep `pos`;
 // pos1 receives the rep of its output and rp the output rep positions.
-static itpp_status build_gate(itpp_ctx c, int i, const std::vector<int>& pos, double dtau, bool spec,
+static itpp_status build_gate(itpp_ctx c, int i, const std::vector<int>& pos, double dtau, bool spec, int shape,
                               GateParams& gp, std::vector<int>& pos1, RepPos& rp) {
   const int G = (int)c->glist.size();
   const int nbits = c->nbits;
@@ -564,7 +620,7 @@ static itpp_status build_gate(itpp_ctx c, int i, const std::vector<int>& pos, do
     const int q = pos1[t.F[k]];
     gp.qm1[q >> 6] |= 1ull << (q & 63);
   }
-  gp.tile = gate_tile(c->NW);
+  gp.tile = gate_tile(c->NW, shape);
   if (c->epoch % kStatusClearEvery == 0) HIP_TRY(c, launch_clear_status(c->status, c->status_cap, c->stream));
   gp.epoch = c->epoch;
   c->epoch = (c->epoch + 1) & 0x3fffffffu;
@@ -589,7 +645,7 @@ static itpp_status enqueue_gate(itpp_ctx c, double dtau, bool spec) {
   GateParams gp;
   std::vector<int> pos1;
   RepPos rp;
-  itpp_status bs = build_gate(c, i, c->pos, dtau, spec, gp, pos1, rp);
+  itpp_status bs = build_gate(c, i, c->pos, dtau, spec, c->shape, gp, pos1, rp);
   if (bs != ITPP_OK) return bs;
   const int in = c->cur, out = c->cur ^ 1;
   const int pin = c->par, pout = c->par ^ 1;
@@ -602,8 +658,8 @@ static itpp_status enqueue_gate(itpp_ctx c, double dtau, bool spec) {
     HIP_TRY(c, next_event(c, &e2));
     HIP_TRY(c, hipEventRecord(e0, c->stream));
   }
-  HIP_TRY(c, launch_gate(c->NW, c->f32, gp, c->side[in], c->side[out], c->plan + pin, c->plan + pout, c->filt + pin,
-                         c->ctl, c->status, c->part, c->cus * gate_wgs_per_cu(), c->stream));
+  HIP_TRY(c, launch_gate(c->NW, c->f32, c->shape, gp, c->side[in], c->side[out], c->plan + pin, c->plan + pout,
+                         c->filt + pin, c->ctl, c->status, c->part, c->cus * gate_wgs_per_cu(c->shape), c->stream));
   if (c->timing) HIP_TRY(c, hipEventRecord(e1, c->stream));
   HIP_TRY(c, launch_select(c->NW, c->f32, c->side[out], c->plan + pout, c->filt + pin, c->filt + pout, c->plan + pin,
                            c->ctl, c->sel, rp, c->cfg.max_terms, c->cfg.cap_policy == ITPP_CAP_FAIL ? 1 : 0,
@@ -745,6 +801,10 @@ itpp_status itpp_set_option(itpp_ctx c, int32_t option, double value) {
     case ITPP_OPT_SPEC_MARGIN:
       if (!(value > 0.0) || !(value <= 1.0)) return fail(c, ITPP_ERR_ARG, "margin must be in (0, 1]");
       c->spec_mult = value;
+      return ITPP_OK;
+    case ITPP_OPT_GATE_SHAPE:
+      if (value != 0.0 && value != 1.0) return fail(c, ITPP_ERR_ARG, "gate shape must be 0 or 1");
+      c->shape = (int)value;
       return ITPP_OK;
     default:
       return fail(c, ITPP_ERR_ARG, "unknown option");
@@ -933,7 +993,7 @@ itpp_status adjoint_gate(itpp_ctx c, int64_t g, const Snapshot& Sin, const Snaps
   GateParams gp;
   std::vector<int> pos1;
   RepPos rp;
-  itpp_status bs = build_gate(c, i, Sin.pos, c->fwd_dtau, false, gp, pos1, rp);
+  itpp_status bs = build_gate(c, i, Sin.pos, c->fwd_dtau, false, 0, gp, pos1, rp);
   if (bs != ITPP_OK) return bs;
   HIP_TRY(c, launch_partition(c->NW, gp, Sin.side, Sin.plan, c->ctl, c->part, c->stream));
   AdjArgs a{};
@@ -946,7 +1006,7 @@ itpp_status adjoint_gate(itpp_ctx c, int64_t g, const Snapshot& Sin, const Snaps
   a.ntiles = B.ntiles;
   a.lam_out_len = Sout.count;
   HIP_TRY(c, launch_adjoint_gate(c->NW, gp, Sin.side, Sin.plan, c->plan + (c->par ^ 1), Sin.filt, c->ctl, c->status,
-                                 c->part, a, c->cus * gate_wgs_per_cu(), c->stream));
+                                 c->part, a, c->cus * gate_wgs_per_cu(0), c->stream));
   HIP_TRY(c, launch_adj_reduce(B.part, B.ntiles, B.dtheta + g, B.sdev + (cur ^ 1), c->ctl, c->stream));
   return ITPP_OK;
 }
@@ -1146,6 +1206,194 @@ itpp_status itpp_backward(itpp_ctx c, int32_t m, const uint64_t* x, const uint64
   c->timing = timing;
   if (st != ITPP_OK) c->ready = false;
   return st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches of independent instances.
+
+struct itpp_batch_s {
+  std::vector<itpp_ctx> inst;
+  void* arena = nullptr;
+  int32_t workers = 4;
+  std::string err;
+};
+
+namespace {
+
+itpp_status batch_fail(itpp_batch b, itpp_status s, const std::string& m) {
+  if (b) b->err = m;
+  return s;
+}
+
+// Run fn(i) for every instance on `workers` host threads; instances are
+// taken largest-work first from a shared counter.  Returns the first error.
+template <typename F>
+itpp_status batch_run(itpp_batch b, const std::vector<double>& work, int workers, F fn) {
+  const int n = (int)b->inst.size();
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+  std::atomic<int> next{0};
+  std::vector<itpp_status> res(n, ITPP_OK);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  auto body = [&]() {
+    (void)hipSetDevice(dev);
+    for (;;) {
+      const int k = next.fetch_add(1);
+      if (k >= n) break;
+      res[order[k]] = fn(order[k]);
+    }
+  };
+  const int nt = std::max(1, std::min(workers, n));
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t) th.emplace_back(body);
+  body();
+  for (auto& t : th) t.join();
+  for (int i = 0; i < n; ++i)
+    if (res[i] != ITPP_OK)
+      return batch_fail(b, res[i], "instance " + std::to_string(i) + ": " + b->inst[i]->err);
+  return ITPP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+itpp_status itpp_batch_create(int32_t n_inst, const itpp_config* cfgs, itpp_batch* out) {
+  if (!cfgs || !out || n_inst < 1) return create_fail(ITPP_ERR_ARG, "bad batch arguments");
+  for (int i = 0; i < n_inst; ++i) {
+    itpp_status s = check_config(&cfgs[i]);
+    if (s != ITPP_OK) return s;
+  }
+  int dev = 0;
+  hipDeviceProp_t prop;
+  itpp_status s = device_props(&dev, &prop);
+  if (s != ITPP_OK) return s;
+  std::vector<uint64_t> bytes(n_inst);
+  uint64_t total = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    s = create_impl(&cfgs[i], dev, prop, nullptr, 0, &bytes[i], nullptr);
+    if (s != ITPP_OK) return s;
+    total += bytes[i];
+  }
+  itpp_batch b = new (std::nothrow) itpp_batch_s;
+  if (!b) return ITPP_ERR_OOM;
+  if (hipMalloc(&b->arena, total) != hipSuccess) {
+    (void)hipGetLastError();
+    delete b;
+    return create_fail(ITPP_ERR_OOM, "batch arena of " + std::to_string(total) + " bytes is not available");
+  }
+  uint64_t off = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    itpp_config cfg = cfgs[i];
+    hipStream_t st = nullptr;
+    if (hipStreamCreate(&st) != hipSuccess) {
+      (void)hipGetLastError();
+      itpp_batch_destroy(b);
+      return create_fail(ITPP_ERR_DEVICE, "hipStreamCreate failed");
+    }
+    cfg.stream = st;
+    itpp_ctx c = nullptr;
+    s = create_impl(&cfg, dev, prop, static_cast<uint8_t*>(b->arena) + off, bytes[i], nullptr, &c);
+    if (s != ITPP_OK) {
+      (void)hipStreamDestroy(st);
+      itpp_batch_destroy(b);
+      return s;
+    }
+    c->own_stream = st;
+    b->inst.push_back(c);
+    off += bytes[i];
+  }
+  *out = b;
+  return ITPP_OK;
+}
+
+itpp_status itpp_batch_destroy(itpp_batch b) {
+  if (!b) return ITPP_OK;
+  for (itpp_ctx c : b->inst) itpp_destroy(c);
+  if (b->arena) (void)hipFree(b->arena);
+  delete b;
+  return ITPP_OK;
+}
+
+itpp_ctx itpp_batch_instance(itpp_batch b, int32_t i) {
+  if (!b || i < 0 || i >= (int32_t)b->inst.size()) return nullptr;
+  return b->inst[i];
+}
+
+itpp_status itpp_batch_set_workers(itpp_batch b, int32_t workers) {
+  if (!b) return ITPP_ERR_ARG;
+  if (workers < 1 || workers > 64) return batch_fail(b, ITPP_ERR_ARG, "workers must be in 1..64");
+  b->workers = workers;
+  return ITPP_OK;
+}
+
+itpp_status itpp_batch_evolve(itpp_batch b, const double* dtau, const int64_t* n_steps, itpp_stats* st) {
+  if (!b || !dtau || !n_steps) return ITPP_ERR_ARG;
+  const int n = (int)b->inst.size();
+  std::vector<double> work(n);
+  for (int i = 0; i < n; ++i) work[i] = (double)n_steps[i] * (double)b->inst[i]->glist.size() * b->inst[i]->n;
+  return batch_run(b, work, b->workers, [&](int i) {
+    return itpp_evolve(b->inst[i], dtau[i], n_steps[i], st ? &st[i] : nullptr);
+  });
+}
+
+itpp_status itpp_batch_autotune(itpp_batch b, const double* dtau, int64_t warm_gates, int64_t probe_gates,
+                                int32_t* best_shape, int32_t* best_workers, double* best_rate) {
+  if (!b || !dtau || warm_gates < 0 || probe_gates < 1) return ITPP_ERR_ARG;
+  const int n = (int)b->inst.size();
+  std::vector<double> work(n);
+  for (int i = 0; i < n; ++i) work[i] = (double)b->inst[i]->n;
+  const int shapes[2] = {0, 1};
+  const int wk[4] = {1, 2, 4, 8};
+  double best = -1.0;
+  int bs = 0, bw = b->workers;
+  for (int sh : shapes) {
+    for (int w : wk) {
+      for (itpp_ctx c : b->inst) {
+        c->shape = sh;
+        itpp_status s = itpp_reset(c);
+        if (s != ITPP_OK) return batch_fail(b, s, c->err);
+      }
+      itpp_status s = batch_run(b, work, w, [&](int i) {
+        return itpp_evolve_gates(b->inst[i], dtau[i], warm_gates, nullptr);
+      });
+      if (s != ITPP_OK) return s;
+      std::vector<itpp_stats> st(n);
+      const auto t0 = std::chrono::steady_clock::now();
+      s = batch_run(b, work, w, [&](int i) {
+        return itpp_evolve_gates(b->inst[i], dtau[i], probe_gates, &st[i]);
+      });
+      if (s != ITPP_OK) return s;
+      const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      double tu = 0.0;
+      for (const auto& x : st) tu += x.term_updates;
+      const double rate = dt > 0.0 ? tu / dt : 0.0;
+      if (rate > best) {
+        best = rate;
+        bs = sh;
+        bw = w;
+      }
+    }
+  }
+  for (itpp_ctx c : b->inst) {
+    c->shape = bs;
+    itpp_status s = itpp_reset(c);
+    if (s != ITPP_OK) return batch_fail(b, s, c->err);
+  }
+  b->workers = bw;
+  if (best_shape) *best_shape = bs;
+  if (best_workers) *best_workers = bw;
+  if (best_rate) *best_rate = best;
+  return ITPP_OK;
+}
+
+const char* itpp_batch_last_error(itpp_batch b) {
+  if (!b) return g_create_error.c_str();
+  return b->err.c_str();
 }
 
 }  // extern "C"

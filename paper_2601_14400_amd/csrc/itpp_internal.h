@@ -172,7 +172,7 @@ struct SelBuf {
 hipError_t launch_init(int nw, int f32, Side s0, Plan* plan, Filter* filt, Ctl* ctl, int w0, hipStream_t st);
 hipError_t launch_partition(int nw, const GateParams& gp, Side in, const Plan* plan_in, Ctl* ctl, uint64_t* part,
                             hipStream_t st);
-hipError_t launch_gate(int nw, int f32, const GateParams& gp, Side in, Side out, const Plan* plan_in,
+hipError_t launch_gate(int nw, int f32, int shape, const GateParams& gp, Side in, Side out, const Plan* plan_in,
                        Plan* plan_out, const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part,
                        int grid, hipStream_t st);
 hipError_t launch_select(int nw, int f32, Side out, const Plan* plan_out, const Filter* filt_in,
@@ -195,7 +195,8 @@ hipError_t launch_observe(int nw, int f32, Side s, const Plan* plan, const Filte
 hipError_t launch_export(int nw, int f32, Side s, const Plan* plan, const Filter* filt, const RepPos& rp,
                          uint64_t* ex, uint64_t* ez, double* ec, unsigned long long* count,
                          uint64_t limit, int grid, hipStream_t st);
-int gate_tile(int nw);
-int gate_wgs_per_cu();
+int gate_tile(int nw, int shape);
+int gate_min_tile(int nw);
+int gate_wgs_per_cu(int shape);
 
 }  // namespace itpp

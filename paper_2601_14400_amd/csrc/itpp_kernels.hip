@@ -25,6 +25,8 @@
 // on load with an IEEE division by the previous identity coefficient.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cmath>
 #include <cstdint>
 
@@ -1694,31 +1696,36 @@ __global__ __launch_bounds__(256) void adj_reduce_kernel(const double* part, con
 
 // ---------------------------------------------------------------------------
 // Host launchers.
-#ifndef ITPP_GATE_BLOCK
-#define ITPP_GATE_BLOCK 1024
-#endif
-#ifndef ITPP_TILE_W1
-#define ITPP_TILE_W1 4000
-#endif
-#ifndef ITPP_TILE_W2
-#define ITPP_TILE_W2 2000
-#endif
-// Gate kernel shape: threads per workgroup and merged elements per tile
-// (one- and two-word keys); occupancy is 2048 / kBlock workgroups per CU.
-constexpr int kBlock = ITPP_GATE_BLOCK;
-template <int NW>
-struct TileFor;
+// Gate kernel shapes (threads per workgroup, merged elements per tile for
+// one- and two-word keys).  Shape 0: one 1024-thread workgroup per CU with
+// large tiles (large states); shape 1: two 512-thread workgroups per CU with
+// half-size tiles (more tiles in flight for small states).  The tile LDS of
+// either shape fits the CU's 160 KB at its occupancy.
+template <int SHAPE>
+struct GateShape;
 template <>
-struct TileFor<2> {
-  static constexpr int value = ITPP_TILE_W1;
+struct GateShape<0> {
+  static constexpr int block = 1024, wgs_per_cu = 1;
+  template <int NW>
+  static constexpr int tile() {
+    return NW == 2 ? 4000 : 2000;
+  }
 };
 template <>
-struct TileFor<4> {
-  static constexpr int value = ITPP_TILE_W2;
+struct GateShape<1> {
+  static constexpr int block = 512, wgs_per_cu = 2;
+  template <int NW>
+  static constexpr int tile() {
+    return NW == 2 ? 2000 : 1500;
+  }
 };
 
-int gate_tile(int nw) { return nw == 2 ? TileFor<2>::value : TileFor<4>::value; }
-int gate_wgs_per_cu() { return 1024 / kBlock; }
+int gate_tile(int nw, int shape) {
+  if (shape == 1) return nw == 2 ? GateShape<1>::tile<2>() : GateShape<1>::tile<4>();
+  return nw == 2 ? GateShape<0>::tile<2>() : GateShape<0>::tile<4>();
+}
+int gate_min_tile(int nw) { return std::min(gate_tile(nw, 0), gate_tile(nw, 1)); }
+int gate_wgs_per_cu(int shape) { return shape == 1 ? GateShape<1>::wgs_per_cu : GateShape<0>::wgs_per_cu; }
 
 // Instantiations: key words (2: n <= 64, 4: n <= 128) x coefficient type.
 #define ITPP_DISPATCH(nw, f32, KERNEL_CALL)            \
@@ -1760,26 +1767,38 @@ hipError_t launch_partition(int nw, const GateParams& gp, Side in, const Plan* p
   return hipGetLastError();
 }
 
-hipError_t launch_gate(int nw, int f32, const GateParams& gp, Side in, Side out, const Plan* plan_in,
+template <int SHAPE>
+void launch_gate_shape(int nw, int f32, const GateParams& gp, Side in, Side out, const Plan* plan_in,
                        Plan* plan_out, const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part,
                        int grid, hipStream_t st) {
+  using S = GateShape<SHAPE>;
   const AdjArgs none{};
   ITPP_DISPATCH(nw, f32,
-                hipLaunchKernelGGL((gate_kernel<NWC, kBlock, TileFor<NWC>::value, TC, false>), dim3(grid),
-                                   dim3(kBlock), 0, st, gp, in, out, plan_in, plan_out, filt_in,
+                hipLaunchKernelGGL((gate_kernel<NWC, S::block, S::template tile<NWC>(), TC, false>), dim3(grid),
+                                   dim3(S::block), 0, st, gp, in, out, plan_in, plan_out, filt_in,
                                    (const uint64_t*)part, ctl, status, none));
+}
+
+hipError_t launch_gate(int nw, int f32, int shape, const GateParams& gp, Side in, Side out, const Plan* plan_in,
+                       Plan* plan_out, const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part,
+                       int grid, hipStream_t st) {
+  if (shape == 1)
+    launch_gate_shape<1>(nw, f32, gp, in, out, plan_in, plan_out, filt_in, ctl, status, part, grid, st);
+  else
+    launch_gate_shape<0>(nw, f32, gp, in, out, plan_in, plan_out, filt_in, ctl, status, part, grid, st);
   return hipGetLastError();
 }
 
 hipError_t launch_adjoint_gate(int nw, const GateParams& gp, Side in, const Plan* plan_in, Plan* plan_scratch,
                                const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part,
                                const AdjArgs& adj, int grid, hipStream_t st) {
+  using S = GateShape<0>;
   const Side none{};
   if (nw == 2)
-    hipLaunchKernelGGL((gate_kernel<2, kBlock, TileFor<2>::value, double, true>), dim3(grid), dim3(kBlock), 0, st,
+    hipLaunchKernelGGL((gate_kernel<2, S::block, S::tile<2>(), double, true>), dim3(grid), dim3(S::block), 0, st,
                        gp, in, none, plan_in, plan_scratch, filt_in, (const uint64_t*)part, ctl, status, adj);
   else
-    hipLaunchKernelGGL((gate_kernel<4, kBlock, TileFor<4>::value, double, true>), dim3(grid), dim3(kBlock), 0, st,
+    hipLaunchKernelGGL((gate_kernel<4, S::block, S::tile<4>(), double, true>), dim3(grid), dim3(S::block), 0, st,
                        gp, in, none, plan_in, plan_scratch, filt_in, (const uint64_t*)part, ctl, status, adj);
   return hipGetLastError();
 }
