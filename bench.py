@@ -13,6 +13,16 @@ roofline object reports the gate kernel's algorithmic bytes per launch
 ((strings in + strings out) * 24 B) over its average launch time, measured
 with HIP events on the engine's stream; the CPU baseline is the plain C++
 dictionary oracle on a bounded prefix of the same workload.
+
+--form selects one of the method's forms instead, each against the plain
+FP64 form on the same GPU (one step = one whole run of its workload):
+  fp32     n=128 periodic TFIM, dtau 0.01, beta 1, threshold 1e-7, cap 2^27,
+           binary32 coefficients; error of every observable vs FP64;
+  batched  64 periodic TFIM instances (n in {16..128}, h, beta drawn from
+           seed 1), cap 2^20 each: one batch vs a loop of single runs;
+  adjoint  n=64 periodic TFIM, beta 1.5, cap 2^24: forward with checkpoints
+           every 10 Trotter steps plus the reverse sweep of <H>, vs the plain
+           forward; d<H>/dJ, d<H>/dh, d<H>/dbeta.
 """
 from __future__ import annotations
 
@@ -33,13 +43,19 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 2; 1 for --form)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 1; 0 for --form)")
     ap.add_argument("--K", type=int, default=1 << 24, help="term cap (default 2^24)")
     ap.add_argument("--beta", type=float, default=2.0, help="final inverse temperature (default 2)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    return ap.parse_args()
+    ap.add_argument("--form", choices=["fp64", "fp32", "batched", "adjoint"], default="fp64")
+    args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 2 if args.form == "fp64" else 1
+    if args.warmup is None:
+        args.warmup = 1 if args.form == "fp64" else 0
+    return args
 
 
 def cpu_baseline(w, budget_s: float):
@@ -48,7 +64,7 @@ def cpu_baseline(w, budget_s: float):
     from oracle import c_oracle
 
     c_oracle.build(force=False)
-    o = c_oracle.COracle(w.n)
+    o = c_oracle.COracle(w.n, w.precision)
     t0 = time.perf_counter()
     steps = 0
     while steps < w.n_steps and time.perf_counter() - t0 < budget_s:
@@ -62,6 +78,189 @@ def cpu_baseline(w, budget_s: float):
                       f"host {platform.processor() or platform.machine()}, os.cpu_count()={os.cpu_count()}"}
 
 
+def roofline_of(tim, peak=HBM_PEAK_GBS):
+    launches = max(1, tim["gate_launches"])
+    avg_ms = tim["gate_ms"] / launches
+    bpl = tim["alg_bytes"] / launches
+    achieved = bpl / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    return {"bound": "hbm", "achieved": achieved, "peak": peak, "unit": "GB/s", "frac": achieved / peak,
+            "traffic": None, "kernel": "gate_kernel", "avg_launch_ms": avg_ms, "alg_bytes_per_launch": bpl,
+            "launches": tim["gate_launches"]}
+
+
+_T0 = time.perf_counter()
+
+
+def progress(msg):
+    print(f"[bench {time.perf_counter() - _T0:8.1f}s] {msg}", file=sys.stderr, flush=True)
+
+
+def base_line(args, metric_value, ms, dtype, config):
+    return {"metric": "pauli_term_updates_per_sec", "value": metric_value, "unit": "term-updates/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config}
+
+
+def run_form_fp32(args):
+    import torch
+
+    import itpp_workloads as W
+    import paper_2601_14400_amd as P
+
+    K = args.K if args.K != (1 << 24) else (1 << 27)
+    out = {}
+    vals = {}
+    for prec in ("f32", "f64"):
+        w = W.config3(K=K, beta=args.beta if args.beta != 2.0 else 1.0, precision=prec)
+        eng = P.engine_for(w)
+        obs = w.observables
+        for _ in range(args.warmup):
+            eng.reset()
+            eng.evolve(w.dtau, w.n_steps)
+        torch.cuda.synchronize()
+        eng.set_timing(True)
+        t0 = time.perf_counter()
+        tu = 0.0
+        for _ in range(args.steps):
+            eng.reset()
+            for s in range(w.n_steps):
+                st = eng.evolve(w.dtau, 1)
+                tu += st["term_updates"]
+                if s % 10 == 9:
+                    progress(f"{prec} step {s + 1}/{w.n_steps} terms {st['n_terms']}")
+            vals[prec] = {k: eng.expect(a, b) for k, (a, b) in obs.items()}
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[prec] = {"value": tu / dt, "ms": dt * 1e3 / args.steps, "roofline": roofline_of(eng.timing()),
+                     "final_terms": st["n_terms"], "w": w}
+        eng.close()
+    w = out["f32"]["w"]
+    line = base_line(args, out["f32"]["value"], out["f32"]["ms"], "f32",
+                     {"workload": f"tfim_n{w.n}_periodic_first_order_dtau{w.dtau}_beta{w.n_steps * w.dtau:g}"
+                                  f"_delta{w.delta:g}_K{K}", "form": "fp32", "n_qubits": w.n, "K": K,
+                      "trotter_steps": w.n_steps})
+    line["roofline"] = out["f32"]["roofline"]
+    line["form"] = {"fp64_value": out["f64"]["value"], "fp32_over_fp64": out["f32"]["value"] / out["f64"]["value"],
+                    "fp64_roofline_frac": out["f64"]["roofline"]["frac"],
+                    "observables_fp32": vals["f32"], "observables_fp64": vals["f64"],
+                    "abs_error_vs_fp64": {k: abs(vals["f32"][k] - vals["f64"][k]) for k in vals["f32"]}}
+    return line, w
+
+
+def run_form_batched(args):
+    import torch
+
+    import itpp_workloads as W
+    import paper_2601_14400_amd as P
+
+    K = args.K if args.K != (1 << 24) else (1 << 20)
+    ws = W.config4_instances(seed=1, count=64, K=K)
+    dts = [w.dtau for w in ws]
+    steps = [w.n_steps for w in ws]
+    # single runs, one after another
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tu_seq = 0.0
+    for i, w in enumerate(ws):
+        e = P.engine_for(w)
+        tu_seq += e.evolve(w.dtau, w.n_steps)["term_updates"]
+        e.close()
+        if i % 8 == 7:
+            progress(f"sequential {i + 1}/64")
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    b = P.batch_for(ws)
+    shape, workers, rate = b.autotune(dts, 200, 200)
+    progress(f"autotune: shape {shape} workers {workers} probe rate {rate:.3e}")
+    for _ in range(args.warmup):
+        for e in b.instances:
+            e.reset()
+        b.evolve(dts, steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tu = 0.0
+    for _ in range(args.steps):
+        for e in b.instances:
+            e.reset()
+        st = b.evolve(dts, steps)
+        tu += sum(x["term_updates"] for x in st)
+        progress("batch done")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # gate-kernel roofline of one instance of the largest size, timed alone
+    big = max(ws, key=lambda w: w.n * w.n_steps)
+    progress(f"roofline run: n={big.n}, {big.n_steps} steps")
+    e = P.engine_for(big)
+    e.set_option("gate_shape", shape)
+    e.set_timing(True)
+    e.evolve(big.dtau, big.n_steps)
+    roof = roofline_of(e.timing())
+    e.close()
+    line = base_line(args, tu / dt, dt * 1e3 / args.steps, "f64",
+                     {"workload": f"tfim_batch64_periodic_n16-128_dtau0.02_delta1e-6_K{K}_seed1", "form": "batched",
+                      "instances": 64, "K": K, "gates": int(sum(2 * w.n * w.n_steps for w in ws))})
+    line["roofline"] = roof
+    line["form"] = {"sequential_value": tu_seq / t_seq, "sequential_s": t_seq, "batched_s": dt / args.steps,
+                    "batched_over_sequential": (tu / dt) / (tu_seq / t_seq), "autotune_shape": shape,
+                    "autotune_workers": workers}
+    return line, big
+
+
+def run_form_adjoint(args):
+    import torch
+
+    import itpp_workloads as W
+    import paper_2601_14400_amd as P
+
+    K = args.K
+    w = W.config5(K=K)
+    nzz = w.n
+    H = (w.strings, w.alphas)
+    # plain forward
+    e = P.engine_for(w)
+    e.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = e.evolve(w.dtau, w.n_steps)
+    E_plain = e.expect(*H)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    roof = roofline_of(e.timing())
+    e.close()
+    progress(f"plain forward {t_fwd:.2f} s")
+    # forward with checkpoints + reverse sweep
+    e = P.engine_for(w)
+    e.set_adjoint(10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st2 = e.evolve(w.dtau, w.n_steps)
+    torch.cuda.synchronize()
+    t_fwd_ck = time.perf_counter() - t0
+    progress(f"checkpointed forward {t_fwd_ck:.2f} s")
+    t0 = time.perf_counter()
+    L, da, dd, _ = e.backward(*H)
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    progress(f"reverse sweep {t_bwd:.2f} s")
+    zz = sum(e.expect([w.strings[k]], [1.0]) for k in range(nzz))
+    xx = sum(e.expect([w.strings[k]], [1.0]) for k in range(nzz, 2 * nzz))
+    e.close()
+    beta = w.dtau * w.n_steps
+    dE_dJ = -zz - float(sum(da[:nzz]))
+    dE_dh = -xx - float(sum(da[nzz:]))
+    dE_db = dd / w.n_steps
+    line = base_line(args, st2["term_updates"] / (t_fwd_ck + t_bwd), (t_fwd_ck + t_bwd) * 1e3, "f64",
+                     {"workload": f"tfim_n64_periodic_first_order_dtau0.02_beta1.5_delta1e-6_K{K}", "form": "adjoint",
+                      "n_qubits": w.n, "K": K, "trotter_steps": w.n_steps, "checkpoint_every_steps": 10})
+    line["roofline"] = roof
+    line["form"] = {"plain_forward_s": t_fwd, "plain_forward_value": st["term_updates"] / t_fwd,
+                    "checkpointed_forward_s": t_fwd_ck, "reverse_sweep_s": t_bwd,
+                    "backward_over_forward": t_bwd / t_fwd, "energy": L, "energy_plain_forward": E_plain,
+                    "dE_dJ": dE_dJ, "dE_dh": dE_dh, "dE_dbeta": dE_db, "specific_heat": -beta * beta * dE_db}
+    return line, w
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -70,6 +269,15 @@ def main():
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     import torch
+
+    if args.form != "fp64":
+        torch.cuda.set_device(0)
+        line, w = {"fp32": run_form_fp32, "batched": run_form_batched, "adjoint": run_form_adjoint}[args.form](args)
+        if not args.no_cpu_baseline:
+            progress("cpu baseline")
+            line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        print(json.dumps(line), flush=True)
+        return
 
     import itpp_workloads as W
     import paper_2601_14400_amd as P
