@@ -59,21 +59,23 @@ def parse():
 
 
 def cpu_baseline(w, budget_s: float):
-    """The C++ dictionary oracle, single-threaded, on the first Trotter steps
-    of the same workload until the time budget is used."""
+    """The C++ dictionary oracle, single-threaded, gate by gate from rho = I
+    along the same workload until the time budget is used."""
     from oracle import c_oracle
 
     c_oracle.build(force=False)
     o = c_oracle.COracle(w.n, w.precision)
     t0 = time.perf_counter()
-    steps = 0
-    while steps < w.n_steps and time.perf_counter() - t0 < budget_s:
-        o.evolve(w.strings, w.alphas, w.schedule, w.dtau, 1, w.delta, w.K)
-        steps += 1
+    gates = 0
+    total = w.n_steps * len(w.schedule)
+    while gates < total and time.perf_counter() - t0 < budget_s:
+        k, m = w.schedule[gates % len(w.schedule)]
+        o.evolve(w.strings, w.alphas, [(k, m)], w.dtau, 1, w.delta, w.K)
+        gates += 1
     dt = time.perf_counter() - t0
     tu = o.term_updates()
     return {"value": tu / dt, "unit": "term-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"C++ dict oracle, Trotter steps 1-{steps} of the same workload "
+            "sample": f"C++ dict oracle, the first {gates} elementary gates of the same workload from rho = I "
                       f"({tu:.3e} term updates in {dt:.1f} s, {o.size()} strings at the end); "
                       f"host {platform.processor() or platform.machine()}, os.cpu_count()={os.cpu_count()}"}
 
@@ -171,7 +173,7 @@ def run_form_batched(args):
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     b = P.batch_for(ws)
-    shape, workers, rate = b.autotune(dts, 200, 200)
+    shape, workers, rate = b.autotune(dts, 60, 60)
     progress(f"autotune: shape {shape} workers {workers} probe rate {rate:.3e}")
     for _ in range(args.warmup):
         for e in b.instances:

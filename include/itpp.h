@@ -239,7 +239,7 @@ itpp_status itpp_batch_set_workers(itpp_batch b, int32_t workers);
 itpp_status itpp_batch_evolve(itpp_batch b, const double* dtau, const int64_t* n_steps, itpp_stats* st);
 
 /* Autotuner: for every gate kernel shape (ITPP_OPT_GATE_SHAPE 0, 1) and
- * 1, 2, 4, 8 workers, reset all instances, apply warm_gates gates untimed,
+ * 2, 4, 8 workers, reset all instances, apply warm_gates gates untimed,
  * then time probe_gates more gates on every instance; keep the combination
  * with the most term updates per second (written to the non-NULL outputs).
  * Leaves every instance reset with the chosen shape. */

@@ -1348,7 +1348,7 @@ itpp_status itpp_batch_autotune(itpp_batch b, const double* dtau, int64_t warm_g
   std::vector<double> work(n);
   for (int i = 0; i < n; ++i) work[i] = (double)b->inst[i]->n;
   const int shapes[2] = {0, 1};
-  const int wk[4] = {1, 2, 4, 8};
+  const int wk[3] = {2, 4, 8};
   double best = -1.0;
   int bs = 0, bw = b->workers;
   for (int sh : shapes) {

@@ -460,8 +460,24 @@ struct GateSmem {
   uint32_t excl[2 * kMaxClasses];
   uint32_t tile;
   uint32_t nwritten, nabove;
+  uint64_t pf[4];  // merge-path bounds of the tile: i0, j0, i1, j1
   JoinLayout L;
 };
+
+// Take the next tile ticket and read its merge-path bounds (one thread).
+__device__ __forceinline__ void take_ticket(const JoinLayout& L, const uint64_t* __restrict__ part, Ctl* ctl,
+                                            uint32_t& t, uint64_t pf[4]) {
+  t = atomicAdd(&ctl->ticket, 1u);
+  const uint64_t total = L.tiles_before[L.njoin];
+  pf[0] = pf[1] = pf[2] = pf[3] = 0;
+  if (t < total) {
+    int j = 0;
+    while (j + 1 < L.njoin && t >= L.tiles_before[j + 1]) ++j;
+    const uint64_t pb = L.tiles_before[j] + (uint64_t)j + (t - L.tiles_before[j]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pf[q] = part[2 * pb + q];
+  }
+}
 
 __device__ __forceinline__ uint64_t phys_sel(const ClassView& v, uint64_t i) {
   uint64_t b = v.base[0], st = 0;
@@ -697,10 +713,17 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
     if (blockIdx.x == 0 && tid == 0) *adj.ntiles = total_tiles;
   }
   if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kErrNone || ctl->halt) return;
+  if (tid == 0) {
+    uint32_t t0;
+    uint64_t pf[4];
+    take_ticket(sm.L, part, ctl, t0, pf);
+    sm.tile = t0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sm.pf[q] = pf[q];
+  }
+  __syncthreads();
 
   for (;;) {
-    if (tid == 0) sm.tile = atomicAdd(&ctl->ticket, 1u);
-    __syncthreads();
     const uint64_t t = sm.tile;
     if (t >= total_tiles) break;
     if (t >= gp.status_cap) {
@@ -713,10 +736,10 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
     const int cA = j, cB = j ^ full;
     const ClassView VA = sm.L.views[cA];
     const ClassView VB = sm.L.views[cB];
-    const uint64_t pb = sm.L.tiles_before[j] + (uint64_t)j + tl;
-    const uint64_t i0 = part[2 * pb], j0 = part[2 * pb + 1];
-    const int nAt = (int)(part[2 * pb + 2] - i0);
-    const int nBt = (int)(part[2 * pb + 3] - j0);
+    (void)tl;
+    const uint64_t i0 = sm.pf[0], j0 = sm.pf[1];
+    const int nAt = (int)(sm.pf[2] - i0);
+    const int nBt = (int)(sm.pf[3] - j0);
     const int nt = nAt + nBt;
     if (nt > TILE + 1 || nAt < 0 || nBt < 0) {
       if (tid == 0) atomicMax(&ctl->error, kErrCapacity);
@@ -1017,9 +1040,36 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
         }
       }
     }
+    if constexpr (!ADJ) {
+      // while wave 0 looks back, the other waves move the keys of the
+      // elements with outputs into the next rep (one bit move per element)
+      // and note the flip pattern of the gate after next (info bits 10-11)
+      for (int x = tid; x < nt; x += BLOCK) {
+        const uint16_t inf = sm.info[x];
+        if (!(inf & (8u | 64u))) continue;
+        const Key<NW> k = lds_key<NW, TILE>(sm.key, x);
+        Key<NW> mk = k;
+        for (int mm = 0; mm < gp.w1; ++mm) mk = move_top(mk, gp.mv[mm], nbits);
+        const Key<NW> ownk = x < nAt ? k : xor_top(k, nbits, w);
+        int fself = 0;
+        for (int bq = 0; bq < gp.w2; ++bq) fself |= get_bit(ownk, gp.fposg[bq]) << bq;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) sm.key[q][x] = mk.w[q];
+        sm.info[x] = (uint16_t)(inf | (fself << 10));
+      }
+    }
     __syncthreads();
     if constexpr (ADJ) {
       adjoint_tile<NW, BLOCK, TILE, T>(sm, adj, gp, fin, ch, sh, t, nAt, nt, i0, j0, VA, VB, cA, cB, ctl);
+      if (tid == 0) {
+        uint32_t tn;
+        uint64_t pf[4];
+        take_ticket(sm.L, part, ctl, tn, pf);
+        sm.tile = tn;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sm.pf[q] = pf[q];
+      }
+      __syncthreads();
       continue;
     }
     // (4) write outputs
@@ -1028,20 +1078,16 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
       const uint16_t inf = sm.info[x];
       if (!(inf & (8u | 64u))) continue;
       const bool isA = x < nAt;
-      const Key<NW> k = lds_key<NW, TILE>(sm.key, x);
       const bool paired = (inf >> 2) & 1;
       T vs, vb;
       values_from<T>(sm.coef[x], (inf >> 1) & 1, paired, paired ? sm.coef[sm.partner[x]] : (T)0, (inf >> 9) & 1,
                      ch, sh, vs, vb);
-      // next-rep keys: one bit move; the two outputs differ by this gate's mask
-      Key<NW> mk = k;
-      for (int mm = 0; mm < gp.w1; ++mm) mk = move_top(mk, gp.mv[mm], nbits);
+      // next-rep keys: the two outputs differ by this gate's mask
+      const Key<NW> mk = lds_key<NW, TILE>(sm.key, x);
       Key<NW> mq = mk;
 #pragma unroll
       for (int q = 0; q < NW; ++q) mq.w[q] ^= gp.qm1[q];
-      const Key<NW> ownk = isA ? k : xor_top(k, nbits, w);
-      int fself = 0;
-      for (int bq = 0; bq < gp.w2; ++bq) fself |= get_bit(ownk, gp.fposg[bq]) << bq;
+      const int fself = (inf >> 10) & 3;
       if (inf & 8u) {
         const int es = (inf >> 4) & 3;
         const int stream = isA ? 0 : 1;
@@ -1086,6 +1132,17 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
     }
     if (written) atomicAdd(&sm.nwritten, written);
     if (above) atomicAdd(&sm.nabove, above);
+    // the next ticket is taken only once this tile's work is done, so tiles
+    // start in ticket order (the look-back relies on it); t and the bounds
+    // were read into registers at the top of this tile
+    if (tid == BLOCK - 1) {
+      uint32_t tn;
+      uint64_t pf[4];
+      take_ticket(sm.L, part, ctl, tn, pf);
+      sm.tile = tn;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sm.pf[q] = pf[q];
+    }
     __syncthreads();
   }
   // flush per-workgroup statistics
