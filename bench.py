@@ -38,6 +38,72 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2601_14400_amd/csrc/itpp_kernels.hip", "paper_2601_14400_amd/csrc/itpp_internal.h")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "gate_kernel_traffic_tfim_n64_open_K2e24.json")
+COPY_BYTES = 256 << 20
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per gate-kernel launch from the committed counter record, if
+    it was taken on the current kernel source (else None)."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return rec
+
+
+def summarize_pmc(fetch_csv: str, write_csv: str):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the gate kernel, each
+    scaled by bytes / counter of the device copies of known size."""
+    import csv
+
+    def read(path):
+        rows = {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                d = int(r["Dispatch_Id"])
+                rows.setdefault(d, [r["Kernel_Name"], 0.0])
+                rows[d][1] += float(r["Counter_Value"])
+        return rows
+
+    out = {}
+    for name, path in (("fetch", fetch_csv), ("write", write_csv)):
+        rows = read(path)
+        items = sorted(rows.items())
+        gate_ids = [d for d, (k, _) in items if "gate_kernel" in k and "true" not in k]
+        gate = [rows[d][1] for d in gate_ids]
+        # the copy dispatches after the last gate launch are the calibration:
+        # three copies of COPY_BYTES
+        tail = [v for d, (k, v) in items if "copyBuffer" in k and d > gate_ids[-1]]
+        per_copy_kib = sum(tail) / 3.0
+        factor = (COPY_BYTES / 1024.0) / per_copy_kib
+        out[name] = {"launches": len(gate), "mean_kib_per_launch": sum(gate) / max(1, len(gate)),
+                     "copy_kib_per_256MiB": per_copy_kib, "factor": factor}
+    bpl = (out["fetch"]["mean_kib_per_launch"] * out["fetch"]["factor"] +
+           out["write"]["mean_kib_per_launch"] * out["write"]["factor"]) * 1024.0
+    rec = {"kernel": "gate_kernel", "workload": "tfim_n64_open_strang_dtau0.02_beta2.0_delta1e-6_K16777216",
+           "kernel_source_sha256": kernel_source_hash(), "bytes_per_launch": bpl, "counters": out,
+           "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- "
+                        "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --calibration-copy",
+                        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- "
+                        "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --calibration-copy"]}
+    with open(TRAFFIC_RECORD, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec, indent=1))
 
 
 def parse():
@@ -50,6 +116,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--form", choices=["fp64", "fp32", "batched", "adjoint"], default="fp64")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="end with three 256 MiB device copies (the byte counters' calibration in a --pmc run)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU: turn the counter_collection.csv of a FETCH_SIZE and a WRITE_SIZE run of this "
+                         "benchmark (with --calibration-copy) into the traffic record under profiles/")
     args = ap.parse_args()
     if args.steps is None:
         args.steps = 2 if args.form == "fp64" else 1
@@ -265,6 +336,9 @@ def run_form_adjoint(args):
 
 def main():
     args = parse()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this engine runs one state on one GPU; multi-GPU runs are not part of it "
@@ -341,6 +415,16 @@ def main():
                    "gate_ms_total": tim["gate_ms"], "select_ms_total": tim["select_ms"],
                    "observables": vals},
     }
+    rec = measured_traffic()
+    if rec is not None and args.K == (1 << 24) and args.beta == 2.0:
+        out["roofline"]["traffic"] = rec["bytes_per_launch"]
+        out["roofline"]["traffic_over_alg"] = rec["bytes_per_launch"] / bytes_per_launch
+    if args.calibration_copy:
+        x = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
