@@ -1457,13 +1457,20 @@ __global__ __launch_bounds__(1024) void select_exact(Side out, Filter* filt_out,
   if (ctl->error || ctl->halt || ctl->sel_need == 0) return;
   const int tid = threadIdx.x;
   const uint64_t m = ctl->cand_count < sel.cap ? ctl->cand_count : sel.cap;
-  uint64_t prefix = 0, mask = 0, need = ctl->sel_need;
-  uint32_t count_eq = 0;
-  const int shifts[6] = {53, 42, 31, 20, 9, 0};
-  const int widths[6] = {11, 11, 11, 11, 11, 9};
-  for (int pass = 0; pass < 6; ++pass) {
-    const int sh = shifts[pass];
-    const int nb = 1 << widths[pass];
+  uint64_t need = ctl->sel_need;
+  // every candidate lies in [sel_lo, sel_hi): the bits above the highest bit
+  // in which sel_lo and sel_hi - 1 differ are common, so the radix passes
+  // start below them (up to 11 bits per pass)
+  const uint64_t diff = ctl->sel_lo ^ (ctl->sel_hi - 1ull);
+  int rem = diff ? 64 - __clzll((long long)diff) : 0;
+  uint64_t mask = rem >= 64 ? 0ull : ~((1ull << rem) - 1ull);
+  uint64_t prefix = ctl->sel_lo & mask;
+  uint32_t count_eq = (uint32_t)m;
+  while (rem > 0) {
+    const int wbits = rem >= 11 ? 11 : rem;
+    const int sh = rem - wbits;
+    rem = sh;
+    const int nb = 1 << wbits;
     const uint64_t dm = (uint64_t)nb - 1ull;
     for (int i = tid; i < 2048; i += blockDim.x) h[i] = 0;
     if (tid == 0) {
