@@ -1421,23 +1421,35 @@ __global__ void select_collect(Side out, const Plan* plan, Ctl* ctl, SelBuf sel)
   const uint64_t lo = ctl->sel_lo, hi = ctl->sel_hi;
   const Plan& p = *plan;
   const int nc = 1 << p.wc, ne = 1 << p.we;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;  // a multiple of 64
+  const int lane = threadIdx.x & 63;
   for (int c = 0; c < nc; ++c)
     for (int e = 0; e < ne; ++e) {
       const uint64_t base = p.base[c][e];
       const uint64_t cnt = p.cnt[c][e];
-      for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
-        const uint64_t idx = base + i;
-        const uint64_t b = abs_bits((double)coefs<T>(out)[idx]);
-        if (b < lo || b >= hi) continue;
-        Key<NW> k = load_key<NW>(out, idx);
-        if (key_zero(k)) continue;
-        const unsigned long long slot = atomicAdd((unsigned long long*)&ctl->cand_count, 1ull);
-        if (slot < sel.cap) {
-          sel.cand_bits[slot] = b;
-          sel.cand_idx[slot] = idx;
-        } else {
-          atomicMax(&ctl->error, kErrCapacity);
+      // wave-uniform loop; one atomic per wave reserves the wave's slots
+      for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); i0 < cnt; i0 += stride) {
+        const uint64_t i = i0 + lane;
+        bool want = false;
+        uint64_t b = 0;
+        if (i < cnt) {
+          b = abs_bits((double)coefs<T>(out)[base + i]);
+          // the identity is the first string of region (0, 0)
+          want = b >= lo && b < hi && !(c == 0 && e == 0 && i == 0);
+        }
+        const uint64_t mk = __ballot(want);
+        if (mk == 0) continue;
+        unsigned long long first = 0;
+        if (lane == 0) first = atomicAdd((unsigned long long*)&ctl->cand_count, (unsigned long long)__popcll(mk));
+        first = __shfl(first, 0, 64);
+        if (want) {
+          const unsigned long long slot = first + (unsigned long long)__popcll(mk & ((1ull << lane) - 1ull));
+          if (slot < sel.cap) {
+            sel.cand_bits[slot] = b;
+            sel.cand_idx[slot] = base + i;
+          } else {
+            atomicMax(&ctl->error, kErrCapacity);
+          }
         }
       }
     }
@@ -1454,9 +1466,16 @@ __global__ __launch_bounds__(1024) void select_exact(Side out, Filter* filt_out,
   __shared__ uint64_t s_above;
   __shared__ uint32_t s_cnt0;
   __shared__ unsigned long long s_ntie;
+  // candidates left after the first radix pass, when few enough (bits, index)
+  constexpr uint32_t kLdsCand = 4096;
+  __shared__ uint64_t lb[kLdsCand];
+  __shared__ uint32_t li[kLdsCand];
+  __shared__ uint32_t s_nl;
   if (ctl->error || ctl->halt || ctl->sel_need == 0) return;
   const int tid = threadIdx.x;
   const uint64_t m = ctl->cand_count < sel.cap ? ctl->cand_count : sel.cap;
+  bool in_lds = false;
+  uint32_t nl = 0;
   uint64_t need = ctl->sel_need;
   // every candidate lies in [sel_lo, sel_hi): the bits above the highest bit
   // in which sel_lo and sel_hi - 1 differ are common, so the radix passes
@@ -1478,9 +1497,16 @@ __global__ __launch_bounds__(1024) void select_exact(Side out, Filter* filt_out,
       s_above = 0;
     }
     __syncthreads();
-    for (uint64_t i = tid; i < m; i += blockDim.x) {
-      const uint64_t b = sel.cand_bits[i];
-      if ((b & mask) == prefix) atomicAdd(&h[(b >> sh) & dm], 1u);
+    if (in_lds) {
+      for (uint32_t i = tid; i < nl; i += blockDim.x) {
+        const uint64_t b = lb[i];
+        if ((b & mask) == prefix) atomicAdd(&h[(b >> sh) & dm], 1u);
+      }
+    } else {
+      for (uint64_t i = tid; i < m; i += blockDim.x) {
+        const uint64_t b = sel.cand_bits[i];
+        if ((b & mask) == prefix) atomicAdd(&h[(b >> sh) & dm], 1u);
+      }
     }
     __syncthreads();
     find_from_top(h, nb, 0, need, scr, &s_bin, &s_above);
@@ -1490,6 +1516,22 @@ __global__ __launch_bounds__(1024) void select_exact(Side out, Filter* filt_out,
     prefix |= (uint64_t)d << sh;
     mask |= dm << sh;
     __syncthreads();
+    if (!in_lds && count_eq <= kLdsCand) {
+      // keep only the candidates of the chosen digit, in LDS
+      if (tid == 0) s_nl = 0;
+      __syncthreads();
+      for (uint64_t i = tid; i < m; i += blockDim.x) {
+        const uint64_t b = sel.cand_bits[i];
+        if ((b & mask) == prefix) {
+          const uint32_t slot = atomicAdd(&s_nl, 1u);
+          lb[slot] = b;
+          li[slot] = (uint32_t)i;
+        }
+      }
+      __syncthreads();
+      nl = s_nl;
+      in_lds = true;
+    }
   }
   const uint64_t kth = prefix;
   const uint32_t need_eq = (uint32_t)need;
@@ -1502,9 +1544,10 @@ __global__ __launch_bounds__(1024) void select_exact(Side out, Filter* filt_out,
   __syncthreads();
   if (count_eq <= need_eq) return;
   // ties: gather canonical keys of the elements equal to kth
-  for (uint64_t i = tid; i < m; i += blockDim.x) {
-    if (sel.cand_bits[i] != kth) continue;
-    Key<NW> k = load_key<NW>(out, sel.cand_idx[i]);
+  const uint64_t mt = in_lds ? nl : m;
+  for (uint64_t i = tid; i < mt; i += blockDim.x) {
+    if ((in_lds ? lb[i] : sel.cand_bits[i]) != kth) continue;
+    Key<NW> k = load_key<NW>(out, sel.cand_idx[in_lds ? li[i] : i]);
     Key<NW> ck = to_canonical(k, rp.pos, rp.nbits);
     const unsigned long long slot = atomicAdd(&s_ntie, 1ull);
     for (int q = 0; q < NW; ++q) sel.tie_keys[slot * NW + q] = ck.w[q];
