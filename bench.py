@@ -98,9 +98,9 @@ def summarize_pmc(fetch_csv: str, write_csv: str):
     rec = {"kernel": "gate_kernel", "workload": "tfim_n64_open_strang_dtau0.02_beta2.0_delta1e-6_K16777216",
            "kernel_source_sha256": kernel_source_hash(), "bytes_per_launch": bpl, "counters": out,
            "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- "
-                        "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --calibration-copy",
+                        "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --calibration-copy --progress",
                         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- "
-                        "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --calibration-copy"]}
+                        "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --calibration-copy --progress"]}
     with open(TRAFFIC_RECORD, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec, indent=1))
@@ -116,6 +116,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--form", choices=["fp64", "fp32", "batched", "adjoint"], default="fp64")
+    ap.add_argument("--progress", action="store_true", help="print a line after every tenth of the Trotter steps")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="end with three 256 MiB device copies (the byte counters' calibration in a --pmc run)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -365,7 +366,23 @@ def main():
 
     def one_step():
         eng.reset()
-        st = eng.evolve(w.dtau, w.n_steps)
+        if args.progress:
+            # ten calls of a tenth of the steps, with a line after each
+            tot = None
+            for k in range(10):
+                n = w.n_steps * (k + 1) // 10 - w.n_steps * k // 10
+                sk = eng.evolve(w.dtau, n)
+                if tot is None:
+                    tot = dict(sk)
+                else:
+                    for key in ("n_gates", "term_updates", "alg_bytes", "spec_gates", "spec_retries"):
+                        tot[key] += sk[key]
+                    for key in ("n_terms", "c_identity", "cap_hit"):
+                        tot[key] = sk[key]
+                progress(f"trotter steps {w.n_steps * (k + 1) // 10}/{w.n_steps}")
+            st = tot
+        else:
+            st = eng.evolve(w.dtau, w.n_steps)
         vals = {k: eng.expect(s, c) for k, (s, c) in obs.items() if k in ("energy_per_site", "Z0Z1", "Z0Z8")}
         return st, vals
 

@@ -91,7 +91,7 @@ struct itpp_ctx_s {
   uint32_t epoch = 1;
   uint64_t serial = 1;
   bool speculate = true;
-  double spec_mult = 0.9;
+  double spec_mult = 0.98;
   int64_t retries_total = 0;
   std::string err;
   // timing
