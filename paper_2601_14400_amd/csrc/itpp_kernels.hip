@@ -362,10 +362,11 @@ __device__ inline void make_layout(JoinLayout& L, const Plan* __restrict__ pin, 
 }
 
 // ---------------------------------------------------------------------------
-// Merge-path partition: one wavefront per tile boundary, 64-ary search of the
-// co-rank (number of class-A strings among the first d of the merged
-// sequence, A first on equal keys), then a pair split by the boundary is
-// moved into the earlier tile.
+// Merge-path partition: eight tile boundaries per wavefront, each searched
+// by a group of 8 lanes (8-ary search of the co-rank: the number of class-A
+// strings among the first d of the merged sequence, A first on equal keys;
+// few probes per level keep the scattered key reads small), then a pair
+// split by the boundary is moved into the earlier tile.
 template <int NW>
 __global__ __launch_bounds__(256) void partition_kernel(GateParams gp, Side in, const Plan* __restrict__ plan_in,
                                                          uint64_t* __restrict__ part, Ctl* __restrict__ ctl) {
@@ -374,7 +375,8 @@ __global__ __launch_bounds__(256) void partition_kernel(GateParams gp, Side in, 
   __syncthreads();
   if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kErrNone || ctl->halt) return;
   const int lane = threadIdx.x & 63;
-  const uint64_t b = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int grp = lane >> 3, sl = lane & 7;
+  const uint64_t b = ((uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * 8 + (uint64_t)grp;
   // boundary b -> join j, local boundary tl (join j owns tiles_before[j]+j .. tiles_before[j+1]+j)
   int j = -1;
   uint64_t tl = 0;
@@ -385,40 +387,49 @@ __global__ __launch_bounds__(256) void partition_kernel(GateParams gp, Side in, 
       tl = b - first;
     }
   }
-  if (j < 0) return;
-  if (b >= gp.status_cap + kMaxClasses) {
-    if (lane == 0) atomicMax(&ctl->error, kErrCapacity);
-    return;
+  bool valid = j >= 0;
+  if (valid && b >= gp.status_cap + kMaxClasses) {
+    if (sl == 0) atomicMax(&ctl->error, kErrCapacity);
+    valid = false;
   }
-  const ClassView& VA = L.views[j];
-  const ClassView& VB = L.views[j ^ L.full];
+  const int jj0 = valid ? j : 0;
+  const ClassView& VA = L.views[jj0];
+  const ClassView& VB = L.views[jj0 ^ L.full];
   const uint64_t nA = VA.size(), nB = VB.size(), len = nA + nB;
   const uint64_t d = (tl * (uint64_t)gp.tile < len) ? tl * (uint64_t)gp.tile : len;
   const int nbits = gp.nbits, w = gp.w;
-  uint64_t lo = d > nB ? d - nB : 0;
-  uint64_t hi = d < nA ? d : nA;  // answer in [lo, hi]
-  while (hi > lo) {
+  uint64_t lo = 0, hi = 0;  // answer in [lo, hi]
+  if (valid) {
+    lo = d > nB ? d - nB : 0;
+    hi = d < nA ? d : nA;
+  }
+  // all groups of the wave step together until every search is done
+  while (__ballot(hi > lo) != 0) {
+    const bool active = hi > lo;
     const uint64_t range = hi - lo;
-    const uint64_t step = (range + 63) / 64;
-    const uint64_t i = lo + (uint64_t)lane * step;
+    const uint64_t step = active ? (range + 7) / 8 : 1;
+    const uint64_t i = lo + (uint64_t)sl * step;
     bool pred = false;
-    if (i < hi) {
+    if (active && i < hi) {
       Key<NW> a = load_key<NW>(in, VA.phys(i));
       Key<NW> bb = xor_top(load_key<NW>(in, VB.phys(d - i - 1)), nbits, w);
       pred = !key_less(bb, a);  // A[i] <= B'[d-i-1]: the answer is above i
     }
     const uint64_t mask = __ballot(pred);
-    const int cnt = __popcll(mask);
-    if (step == 1) {
-      lo = lo + (uint64_t)cnt;
-      break;
+    if (active) {
+      const int cnt = __popcll((mask >> (8 * grp)) & 0xffull);
+      if (step == 1) {
+        lo = lo + (uint64_t)cnt;
+        hi = lo;
+      } else {
+        const uint64_t nlo = cnt == 0 ? lo : lo + (uint64_t)(cnt - 1) * step + 1;
+        const uint64_t nhi_c = lo + (uint64_t)cnt * step;
+        hi = nhi_c < hi ? nhi_c : hi;
+        lo = nlo;
+      }
     }
-    const uint64_t nlo = cnt == 0 ? lo : lo + (uint64_t)(cnt - 1) * step + 1;
-    const uint64_t nhi_c = lo + (uint64_t)cnt * step;
-    hi = nhi_c < hi ? nhi_c : hi;
-    lo = nlo;
   }
-  if (lane == 0) {
+  if (valid && sl == 0) {
     uint64_t i = lo, jj = d - lo;
     if (i > 0 && jj < nB) {
       Key<NW> a = load_key<NW>(in, VA.phys(i - 1));
@@ -1427,28 +1438,35 @@ __global__ void select_collect(Side out, const Plan* plan, Ctl* ctl, SelBuf sel)
     for (int e = 0; e < ne; ++e) {
       const uint64_t base = p.base[c][e];
       const uint64_t cnt = p.cnt[c][e];
-      // wave-uniform loop; one atomic per wave reserves the wave's slots
-      for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); i0 < cnt; i0 += stride) {
-        const uint64_t i = i0 + lane;
-        bool want = false;
-        uint64_t b = 0;
-        if (i < cnt) {
-          b = abs_bits((double)coefs<T>(out)[base + i]);
-          // the identity is the first string of region (0, 0)
-          want = b >= lo && b < hi && !(c == 0 && e == 0 && i == 0);
+      // wave-uniform loop over four strided chunks of 64 (their loads are
+      // in flight together); one atomic per wave reserves the wave's slots
+      constexpr int U = 4;
+      for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); i0 < cnt; i0 += U * stride) {
+        uint64_t bv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint64_t i = i0 + (uint64_t)u * stride + lane;
+          bv[u] = i < cnt ? abs_bits((double)coefs<T>(out)[base + i]) : ~0ull;
         }
-        const uint64_t mk = __ballot(want);
-        if (mk == 0) continue;
-        unsigned long long first = 0;
-        if (lane == 0) first = atomicAdd((unsigned long long*)&ctl->cand_count, (unsigned long long)__popcll(mk));
-        first = __shfl(first, 0, 64);
-        if (want) {
-          const unsigned long long slot = first + (unsigned long long)__popcll(mk & ((1ull << lane) - 1ull));
-          if (slot < sel.cap) {
-            sel.cand_bits[slot] = b;
-            sel.cand_idx[slot] = base + i;
-          } else {
-            atomicMax(&ctl->error, kErrCapacity);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint64_t i = i0 + (uint64_t)u * stride + lane;
+          const uint64_t b = bv[u];
+          // the identity is the first string of region (0, 0)
+          const bool want = i < cnt && b >= lo && b < hi && !(c == 0 && e == 0 && i == 0);
+          const uint64_t mk = __ballot(want);
+          if (mk == 0) continue;
+          unsigned long long first = 0;
+          if (lane == 0) first = atomicAdd((unsigned long long*)&ctl->cand_count, (unsigned long long)__popcll(mk));
+          first = __shfl(first, 0, 64);
+          if (want) {
+            const unsigned long long slot = first + (unsigned long long)__popcll(mk & ((1ull << lane) - 1ull));
+            if (slot < sel.cap) {
+              sel.cand_bits[slot] = b;
+              sel.cand_idx[slot] = base + i;
+            } else {
+              atomicMax(&ctl->error, kErrCapacity);
+            }
           }
         }
       }
@@ -1864,9 +1882,9 @@ hipError_t launch_init(int nw, int f32, Side s0, Plan* plan, Filter* filt, Ctl* 
 
 hipError_t launch_partition(int nw, const GateParams& gp, Side in, const Plan* plan_in, Ctl* ctl, uint64_t* part,
                             hipStream_t st) {
-  // one wavefront per tile boundary, four per block
+  // eight tile boundaries per wavefront, four wavefronts per block
   const uint64_t nb = gp.status_cap + kMaxClasses;
-  const int pgrid = (int)((nb + 3) / 4);
+  const int pgrid = (int)((nb + 31) / 32);
   if (nw == 2)
     hipLaunchKernelGGL(partition_kernel<2>, dim3(pgrid), dim3(256), 0, st, gp, in, plan_in, part, ctl);
   else
