@@ -199,7 +199,7 @@ itpp_status itpp_backward(itpp_ctx ctx, int32_t n_strings, const uint64_t* x, co
  *    previous gate; if fewer than K-1 strings pass, the gate is redone
  *    without the margin, so the kept set is always the exact one.
  *  ITPP_OPT_SPEC_MARGIN (default 0.98): that margin as a factor in (0, 1].
- *  ITPP_OPT_GATE_SHAPE (default 0): 0 = one 1024-thread workgroup per CU
+ *  ITPP_OPT_GATE_SHAPE (default 0 for n <= 64, 1 above): 0 = one 1024-thread workgroup per CU
  *    with 4000 (n <= 64) or 2000 (n <= 128) strings per tile; 1 = two
  *    512-thread workgroups per CU with 2000 or 1500 strings per tile (more
  *    tiles in flight, better for small states). */

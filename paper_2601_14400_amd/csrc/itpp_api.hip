@@ -387,6 +387,9 @@ itpp_status create_impl(const itpp_config* cfg, int dev, const hipDeviceProp_t& 
   c->nbits = 2 * c->n;
   c->f32 = cfg->precision == ITPP_F32 ? 1 : 0;
   c->coef_bytes = c->f32 ? 4 : 8;
+  // two-word keys run faster with two 512-thread workgroups per CU (their
+  // larger keys leave fewer registers per thread at 1024 threads)
+  c->shape = c->NW == 4 ? 1 : 0;
   c->stream = static_cast<hipStream_t>(cfg->stream);
   c->device = dev;
   c->cus = prop.multiProcessorCount;
