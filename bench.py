@@ -246,7 +246,7 @@ def run_form_batched(args):
     t_seq = time.perf_counter() - t0
     b = P.batch_for(ws)
     shape, workers, rate = b.autotune(dts, 60, 60)
-    progress(f"autotune: shape {shape} workers {workers} probe rate {rate:.3e}")
+    progress(f"autotune: shapes {shape} (bit 0: n <= 64, bit 1: n > 64) workers {workers} probe rate {rate:.3e}")
     for _ in range(args.warmup):
         for e in b.instances:
             e.reset()
@@ -266,7 +266,7 @@ def run_form_batched(args):
     big = max(ws, key=lambda w: w.n * w.n_steps)
     progress(f"roofline run: n={big.n}, {big.n_steps} steps")
     e = P.engine_for(big)
-    e.set_option("gate_shape", shape)
+    e.set_option("gate_shape", (shape >> 1) & 1 if big.n > 64 else shape & 1)
     e.set_timing(True)
     e.evolve(big.dtau, big.n_steps)
     roof = roofline_of(e.timing())

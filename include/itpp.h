@@ -238,11 +238,13 @@ itpp_status itpp_batch_set_workers(itpp_batch b, int32_t workers);
  * itpp_batch_last_error). */
 itpp_status itpp_batch_evolve(itpp_batch b, const double* dtau, const int64_t* n_steps, itpp_stats* st);
 
-/* Autotuner: for every gate kernel shape (ITPP_OPT_GATE_SHAPE 0, 1) and
- * 2, 4, 8 workers, reset all instances, apply warm_gates gates untimed,
- * then time probe_gates more gates on every instance; keep the combination
- * with the most term updates per second (written to the non-NULL outputs).
- * Leaves every instance reset with the chosen shape. */
+/* Autotuner: for every choice of gate kernel shape (ITPP_OPT_GATE_SHAPE 0
+ * or 1, chosen separately for instances with n <= 64 and n > 64) and 2, 4,
+ * 8 workers, reset all instances, apply warm_gates gates untimed, then time
+ * probe_gates more gates on every instance; keep the combination with the
+ * most term updates per second (written to the non-NULL outputs; best_shape
+ * bit 0 is the shape for n <= 64, bit 1 the shape for n > 64).  Leaves every
+ * instance reset with the chosen shapes. */
 itpp_status itpp_batch_autotune(itpp_batch b, const double* dtau, int64_t warm_gates, int64_t probe_gates,
                                 int32_t* best_shape, int32_t* best_workers, double* best_rate);
 

@@ -1350,14 +1350,14 @@ itpp_status itpp_batch_autotune(itpp_batch b, const double* dtau, int64_t warm_g
   const int n = (int)b->inst.size();
   std::vector<double> work(n);
   for (int i = 0; i < n; ++i) work[i] = (double)b->inst[i]->n;
-  const int shapes[2] = {0, 1};
+  // shape choices: bit 0 for one-word keys (n <= 64), bit 1 for two-word keys
   const int wk[3] = {2, 4, 8};
   double best = -1.0;
   int bs = 0, bw = b->workers;
-  for (int sh : shapes) {
+  for (int sh = 0; sh < 4; ++sh) {
     for (int w : wk) {
       for (itpp_ctx c : b->inst) {
-        c->shape = sh;
+        c->shape = c->NW == 4 ? (sh >> 1) & 1 : sh & 1;
         itpp_status s = itpp_reset(c);
         if (s != ITPP_OK) return batch_fail(b, s, c->err);
       }
@@ -1383,7 +1383,7 @@ itpp_status itpp_batch_autotune(itpp_batch b, const double* dtau, int64_t warm_g
     }
   }
   for (itpp_ctx c : b->inst) {
-    c->shape = bs;
+    c->shape = c->NW == 4 ? (bs >> 1) & 1 : bs & 1;
     itpp_status s = itpp_reset(c);
     if (s != ITPP_OK) return batch_fail(b, s, c->err);
   }
