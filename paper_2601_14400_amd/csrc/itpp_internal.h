@@ -72,6 +72,7 @@ struct Ctl {
   uint32_t pad2;
   uint64_t cand_count;
   uint32_t need_coarse;      // the fine window missed: select from a full histogram
+  uint32_t hist_done;        // workgroups of the full histogram that have finished
   uint32_t pad3;
   double term_updates;
   double alg_elems;          // sum over gates of survivors in + survivors out

@@ -922,7 +922,7 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
             __hip_atomic_store(&status[sd * SN + t], aw[sd], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         // each lane inspects LB consecutive predecessors per round (window 64 * LB)
-        constexpr int LB = 8;
+        constexpr int LB = 2;
         const int64_t first = (int64_t)sm.L.tiles_before[j];
         int64_t khi = (int64_t)t - 1;
         bool done = false;
@@ -1331,7 +1331,7 @@ __global__ __launch_bounds__(1024) void select_decide(const Filter* filt_in, Fil
     ctl->sel_hi = sel_hi;
     ctl->sel_need = (capped && !none_kept) ? (uint32_t)sel_need : 0u;
     ctl->need_coarse = (capped && !none_kept && coarse) ? 1u : 0u;
-    if (ctl->need_coarse) ctl->sel_need = (uint32_t)need;  // resolved by select_coarse_pick
+    if (ctl->need_coarse) ctl->sel_need = (uint32_t)need;  // resolved by select_coarse_hist
     ctl->cand_count = 0;
     ctl->ticket = 0;
     ctl->n_written_nonid = 0;
@@ -1375,12 +1375,18 @@ __global__ void prepare_kernel(Plan* plan_out, Ctl* ctl) {
 }
 
 // Fallback when the K-th value is outside the fine window: full histogram of
-// the stored non-identity |c| values (16 bins per octave).
+// the stored non-identity |c| values (16 bins per octave); the last
+// workgroup to finish picks the bin that holds the (K-1)-th value.
 template <int NW, typename T>
 __global__ __launch_bounds__(256) void select_coarse_hist(Side out, const Plan* plan, Ctl* ctl) {
   __shared__ uint32_t h[kHistBins];
+  __shared__ uint64_t scr[256];
+  __shared__ int s_bin;
+  __shared__ uint64_t s_above;
+  __shared__ uint32_t s_last;
   if (ctl->error || ctl->halt || !ctl->need_coarse) return;
-  for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) h[i] = 0;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kHistBins; i += blockDim.x) h[i] = 0;
   __syncthreads();
   const Plan& p = *plan;
   const int nc = 1 << p.wc, ne = 1 << p.we;
@@ -1389,24 +1395,22 @@ __global__ __launch_bounds__(256) void select_coarse_hist(Side out, const Plan* 
     for (int e = 0; e < ne; ++e) {
       const uint64_t base = p.base[c][e];
       const uint64_t cnt = p.cnt[c][e];
-      for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
+      for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + tid; i < cnt; i += stride) {
         if (c == 0 && e == 0 && i == 0) continue;  // the identity is the first string of region (0,0)
         atomicAdd(&h[hist_bin(abs_bits((double)coefs<T>(out)[base + i]))], 1u);
       }
     }
   __syncthreads();
-  for (int i = threadIdx.x; i < kHistBins; i += blockDim.x)
+  for (int i = tid; i < kHistBins; i += blockDim.x)
     if (h[i]) atomicAdd(&ctl->hist[i], h[i]);
-}
-
-__global__ __launch_bounds__(1024) void select_coarse_pick(Ctl* ctl) {
-  __shared__ uint32_t h[kHistBins];
-  __shared__ uint64_t scr[1024];
-  __shared__ int s_bin;
-  __shared__ uint64_t s_above;
-  if (ctl->error || ctl->halt || !ctl->need_coarse) return;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < kHistBins; i += blockDim.x) h[i] = ctl->hist[i];
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_last = atomicAdd(&ctl->hist_done, 1u) == gridDim.x - 1 ? 1u : 0u;
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  for (int i = tid; i < kHistBins; i += blockDim.x)
+    h[i] = __hip_atomic_load(&ctl->hist[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (tid == 0) {
     s_bin = -1;
     s_above = 0;
@@ -1414,13 +1418,14 @@ __global__ __launch_bounds__(1024) void select_coarse_pick(Ctl* ctl) {
   __syncthreads();
   const uint64_t need = ctl->sel_need;
   find_from_top(h, kHistBins, 0, need, scr, &s_bin, &s_above);
-  const int b = s_bin < 0 ? 0 : s_bin;
+  const int bsel = s_bin < 0 ? 0 : s_bin;
   for (int i = tid; i < kHistBins; i += blockDim.x) ctl->hist[i] = 0;
   if (tid == 0) {
-    ctl->sel_lo = b == 0 ? 0ull : ((uint64_t)(b + kHistBase) << kHistShift);
-    ctl->sel_hi = b == kHistBins - 1 ? ~0ull : ((uint64_t)(b + 1 + kHistBase) << kHistShift);
+    ctl->sel_lo = bsel == 0 ? 0ull : ((uint64_t)(bsel + kHistBase) << kHistShift);
+    ctl->sel_hi = bsel == kHistBins - 1 ? ~0ull : ((uint64_t)(bsel + 1 + kHistBase) << kHistShift);
     ctl->sel_need = (uint32_t)(need - (s_bin < 0 ? 0 : s_above));
     ctl->need_coarse = 0;
+    ctl->hist_done = 0;
   }
 }
 
@@ -1963,8 +1968,8 @@ hipError_t launch_select(int nw, int f32, Side out, const Plan* plan_out, const 
   hipLaunchKernelGGL(select_decide, dim3(1), dim3(1024), 0, st, filt_in, filt_out, plan_next, ctl, K,
                      cap_fail, spec, serial);
   ITPP_DISPATCH(nw, f32, {
-    hipLaunchKernelGGL((select_coarse_hist<NWC, TC>), dim3(grid), dim3(256), 0, st, out, plan_out, ctl);
-    hipLaunchKernelGGL(select_coarse_pick, dim3(1), dim3(1024), 0, st, ctl);
+    hipLaunchKernelGGL((select_coarse_hist<NWC, TC>), dim3(grid / 4 > 0 ? grid / 4 : 1), dim3(256), 0, st, out,
+                       plan_out, ctl);
     hipLaunchKernelGGL((select_collect<NWC, TC>), dim3(grid), dim3(256), 0, st, out, plan_out, ctl, sel);
     hipLaunchKernelGGL(select_exact<NWC>, dim3(1), dim3(1024), 0, st, out, filt_out, ctl, sel, rp);
   });
