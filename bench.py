@@ -38,7 +38,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ("paper_2601_14400_amd/csrc/itpp_kernels.hip", "paper_2601_14400_amd/csrc/itpp_internal.h")
+# the sources the gate kernel is built from (its traffic record is keyed by them)
+KERNEL_SOURCES = ("paper_2601_14400_amd/csrc/itpp_gate.hip", "paper_2601_14400_amd/csrc/itpp_device.h",
+                  "paper_2601_14400_amd/csrc/itpp_internal.h")
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "gate_kernel_traffic_tfim_n64_open_K2e24.json")
 COPY_BYTES = 256 << 20
 

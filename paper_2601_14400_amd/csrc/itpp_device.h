@@ -1,0 +1,366 @@
+// Device-side types and helpers shared by the ITPP kernels (gfx950, wave64):
+// bit-permuted Pauli keys, coefficient arithmetic of the two storage
+// precisions, the deferred filter, class views of a stored state and the
+// join layout of a gate.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "itpp_internal.h"
+
+namespace itpp {
+
+template <int NW>
+struct Key {
+  uint64_t w[NW];
+};
+
+template <int NW>
+__device__ __forceinline__ bool key_less(const Key<NW>& a, const Key<NW>& b) {
+#pragma unroll
+  for (int i = NW - 1; i >= 0; --i)
+    if (a.w[i] != b.w[i]) return a.w[i] < b.w[i];
+  return false;
+}
+
+template <int NW>
+__device__ __forceinline__ bool key_eq(const Key<NW>& a, const Key<NW>& b) {
+  bool e = true;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) e = e && (a.w[i] == b.w[i]);
+  return e;
+}
+
+template <int NW>
+__device__ __forceinline__ bool key_zero(const Key<NW>& a) {
+  uint64_t o = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) o |= a.w[i];
+  return o == 0;
+}
+
+// Bit access at a runtime position without indexing the register array
+// (a dynamic index would move the key to scratch memory).
+template <int NW>
+__device__ __forceinline__ uint64_t word_at(const Key<NW>& k, int wi) {
+  uint64_t v = k.w[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) v = (wi == i) ? k.w[i] : v;
+  return v;
+}
+
+template <int NW>
+__device__ __forceinline__ int get_bit(const Key<NW>& k, int p) {
+  return (int)((word_at(k, p >> 6) >> (p & 63)) & 1ull);
+}
+
+template <int NW>
+__device__ __forceinline__ void xor_bit(Key<NW>& k, int p, uint64_t v) {
+  const int wi = p >> 6;
+  const uint64_t m = v << (p & 63);
+#pragma unroll
+  for (int i = 0; i < NW; ++i) k.w[i] ^= (wi == i) ? m : 0ull;
+}
+
+template <int NW>
+__device__ __forceinline__ void flip_bit(Key<NW>& k, int p) {
+  xor_bit(k, p, 1ull);
+}
+
+// Flip the w most significant meaningful bits (the bits the gate flips).
+template <int NW>
+__device__ __forceinline__ Key<NW> xor_top(Key<NW> k, int nbits, int w) {
+  for (int b = nbits - w; b < nbits; ++b) flip_bit(k, b);
+  return k;
+}
+
+// Class = pattern of the w most significant meaningful bits.
+template <int NW>
+__device__ __forceinline__ int class_of(const Key<NW>& k, int nbits, int w) {
+  int c = 0;
+  for (int b = 0; b < w; ++b) c |= get_bit(k, nbits - w + b) << b;
+  return c;
+}
+
+// Move the bit at position p to position nbits-1; bits above p shift down.
+template <int NW>
+__device__ __forceinline__ Key<NW> move_top(const Key<NW>& k, int p, int nbits) {
+  const uint64_t b = (uint64_t)get_bit(k, p);
+  Key<NW> r;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    uint64_t shr = (k.w[i] >> 1) | ((i + 1 < NW) ? (k.w[i + 1] << 63) : 0ull);
+    const int lo = 64 * i;
+    uint64_t lm;
+    if (p <= lo)
+      lm = 0ull;
+    else if (p >= lo + 64)
+      lm = ~0ull;
+    else
+      lm = (1ull << (p - lo)) - 1ull;
+    r.w[i] = (k.w[i] & lm) | (shr & ~lm);
+  }
+  xor_bit(r, nbits - 1, b);  // bit nbits-1 of the shifted key is zero
+  return r;
+}
+
+template <int NW>
+__device__ __forceinline__ Key<NW> load_key(const Side& s, uint64_t i) {
+  Key<NW> k;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) k.w[w] = s.kw[w][i];
+  return k;
+}
+
+template <int NW>
+__device__ __forceinline__ void store_key(const Side& s, uint64_t i, const Key<NW>& k) {
+#pragma unroll
+  for (int w = 0; w < NW; ++w) s.kw[w][i] = k.w[w];
+}
+
+// Canonical key (x words then z words) of a rep key.
+template <int NW>
+__device__ inline Key<NW> to_canonical(const Key<NW>& k, const uint8_t* pos, int nbits) {
+  Key<NW> c;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) c.w[i] = 0;
+  const int n = nbits / 2;
+  constexpr int W = NW / 2;
+  for (int cb = 0; cb < nbits; ++cb) {
+    if (get_bit(k, pos[cb])) {
+      const int word = (cb < n) ? (cb >> 6) : (W + ((cb - n) >> 6));
+      const int bit = (cb < n) ? (cb & 63) : ((cb - n) & 63);
+      xor_bit(c, 64 * word + bit, 1ull);
+    }
+  }
+  return c;
+}
+
+// Canonical order: x words from the most significant, then z words.
+template <int NW>
+__device__ inline bool canon_le(const Key<NW>& a, const Key<NW>& b) {
+  constexpr int W = NW / 2;
+  for (int i = W - 1; i >= 0; --i)
+    if (a.w[i] != b.w[i]) return a.w[i] < b.w[i];
+  for (int i = W - 1; i >= 0; --i)
+    if (a.w[W + i] != b.w[W + i]) return a.w[W + i] < b.w[W + i];
+  return true;
+}
+
+__device__ __forceinline__ uint64_t abs_bits(double v) {
+  return (uint64_t)__double_as_longlong(v) & 0x7fffffffffffffffull;
+}
+
+// Coefficient arithmetic of the two storage precisions.  Products and sums
+// are rounded to the storage type T; the division by the identity
+// coefficient is done in double and rounded once to T; magnitudes are
+// compared, histogrammed and selected as doubles (exact widening, so the
+// order is that of T).
+__device__ __forceinline__ double mul_rn(double a, double b) { return __dmul_rn(a, b); }
+__device__ __forceinline__ float mul_rn(float a, float b) { return __fmul_rn(a, b); }
+__device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
+__device__ __forceinline__ float add_rn(float a, float b) { return __fadd_rn(a, b); }
+__device__ __forceinline__ double abs_d(double v) { return fabs(v); }
+__device__ __forceinline__ double abs_d(float v) { return (double)fabsf(v); }
+template <typename T>
+__device__ __forceinline__ T normalised(T c, double cI) {
+  return (T)((double)c / cI);
+}
+template <typename T>
+__device__ __forceinline__ T* coefs(const Side& s) {
+  return static_cast<T*>(s.coef);
+}
+
+// Error-free sum (Knuth TwoSum): s + e == a + b exactly.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = __dadd_rn(a, b);
+  const double bb = __dsub_rn(s, a);
+  e = __dadd_rn(__dsub_rn(a, __dsub_rn(s, bb)), __dsub_rn(b, bb));
+}
+
+
+__device__ __forceinline__ int hist_bin(uint64_t bits) {
+  const int64_t b = (int64_t)(bits >> kHistShift) - (int64_t)kHistBase;
+  return b < 0 ? 0 : (b >= kHistBins ? kHistBins - 1 : (int)b);
+}
+
+// Survivor test of a stored element under the filter decided after the gate
+// that produced it (identity always survives; the threshold was applied when
+// writing).
+template <int NW>
+__device__ inline bool survives(const Key<NW>& k, double c, const Filter& f, const uint8_t* pos,
+                                int nbits) {
+  if (!f.cap_active) return true;
+  if (key_zero(k)) return true;
+  const uint64_t b = abs_bits(c);
+  if (b != f.kth_bits) return b > f.kth_bits;
+  if (!f.tie_active) return true;
+  Key<NW> ck = to_canonical(k, pos, nbits);
+  Key<NW> tk;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) tk.w[i] = f.tie_key[i];
+  return canon_le(ck, tk);
+}
+
+// A class of the input as the concatenation of up to kMaxClasses regions.
+struct ClassView {
+  uint64_t base[kMaxClasses];
+  uint64_t start[kMaxClasses + 1];
+  int nseg;
+  __device__ __forceinline__ uint64_t size() const { return start[nseg]; }
+  __device__ __forceinline__ uint64_t phys(uint64_t i) const {
+    int s = 0;
+#pragma unroll
+    for (int t = 1; t < kMaxClasses; ++t)
+      if (t < nseg && i >= start[t]) s = t;
+    return base[s] + (i - start[s]);
+  }
+};
+
+__device__ inline ClassView make_view(const Plan* __restrict__ pp, int cls) {
+  const Plan& p = *pp;
+  ClassView v;
+  const int nc = 1 << p.wc;
+  v.nseg = nc;
+  uint64_t acc = 0;
+  for (int c = 0; c < kMaxClasses; ++c) {
+    v.start[c] = acc;
+    if (c < nc) {
+      v.base[c] = p.base[c][cls];
+      acc += p.cnt[c][cls];
+    } else {
+      v.base[c] = 0;
+    }
+  }
+  v.start[kMaxClasses] = acc;
+#pragma unroll
+  for (int c = 1; c < kMaxClasses; ++c)
+    if (c >= nc) v.start[c] = acc;
+  return v;
+}
+
+// Phase of Q P = sigma R for a commuting P: +1 or -1 (sigma_neg = 1 for -1).
+// e = aQ + sum_j (xP zP - xR zR) + 2 sum_j zQ xP  (mod 4) over the support.
+template <int NW>
+__device__ __forceinline__ int phase_negative(const Key<NW>& k, const GateParams& gp) {
+  int e = gp.aQ;
+  for (int j = 0; j < gp.nsup; ++j) {
+    const int xp = get_bit(k, gp.px[j]);
+    const int zp = get_bit(k, gp.pz[j]);
+    const int xr = xp ^ gp.qx[j];
+    const int zr = zp ^ gp.qz[j];
+    e += (xp & zp) - (xr & zr) + 2 * (gp.qz[j] & xp);
+  }
+  e &= 3;
+  return e;  // 0: +1, 2: -1, odd: error
+}
+
+template <int NW>
+__device__ __forceinline__ bool anticommutes(const Key<NW>& k, const GateParams& gp) {
+  int par = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) par ^= __popcll(k.w[i] & gp.cmask[i]) & 1;
+  return par != 0;
+}
+
+__device__ __forceinline__ uint32_t lane16(uint64_t v, int e) { return (uint32_t)((v >> (16 * e)) & 0xffffull); }
+
+// ---------------------------------------------------------------------------
+// Block-wide exclusive scan of two packed u64 vectors (16-bit lanes).
+template <int BLOCK>
+__device__ inline void block_scan2(uint64_t& a, uint64_t& b, uint64_t* wa, uint64_t* wb,
+                                   uint64_t& tot_a, uint64_t& tot_b) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  constexpr int NWAVE = BLOCK / 64;
+  uint64_t ia = a, ib = b;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint64_t ta = __shfl_up(ia, d, 64);
+    uint64_t tb = __shfl_up(ib, d, 64);
+    if (lane >= d) {
+      ia += ta;
+      ib += tb;
+    }
+  }
+  if (lane == 63) {
+    wa[wid] = ia;
+    wb[wid] = ib;
+  }
+  __syncthreads();
+  uint64_t pa = 0, pb = 0, sa = 0, sb = 0;
+#pragma unroll
+  for (int w = 0; w < NWAVE; ++w) {
+    if (w < wid) {
+      pa += wa[w];
+      pb += wb[w];
+    }
+    sa += wa[w];
+    sb += wb[w];
+  }
+  a = pa + ia - a;
+  b = pb + ib - b;
+  tot_a = sa;
+  tot_b = sb;
+  __syncthreads();
+}
+
+// End (exclusive) of output region (c, e) in the (c major, e minor) layout.
+__device__ __forceinline__ uint64_t region_end(const uint64_t (*ob)[kMaxClasses], int c, int e) {
+  int cc = c, ee = e + 1;
+  if (ee == kMaxClasses) {
+    ee = 0;
+    ++cc;
+  }
+  return ob[cc][ee];
+}
+
+// Join layout shared by the partition and gate kernels: the classes of the
+// gate's input, and for join j (classes j and ~j) its first tile and first
+// boundary index.
+struct JoinLayout {
+  ClassView views[kMaxClasses];
+  uint64_t tiles_before[kMaxClasses / 2 + 1];
+  int njoin, full;
+};
+
+__device__ inline void make_layout(JoinLayout& L, const Plan* __restrict__ pin, int w, int tile) {
+  const int ncls = 1 << w;
+  L.full = ncls - 1;
+  L.njoin = ncls >> 1;
+  for (int c = 0; c < kMaxClasses; ++c) L.views[c] = make_view(pin, c < ncls ? c : 0);
+  L.tiles_before[0] = 0;
+  for (int j = 0; j < kMaxClasses / 2; ++j) {
+    uint64_t len = 0;
+    if (j < L.njoin) len = L.views[j].size() + L.views[j ^ L.full].size();
+    L.tiles_before[j + 1] = L.tiles_before[j] + (len + tile - 1) / tile;
+  }
+}
+
+
+// Instantiations: key words (2: n <= 64, 4: n <= 128) x coefficient type.
+#define ITPP_DISPATCH(nw, f32, KERNEL_CALL)            \
+  do {                                                  \
+    if (nw == 2 && !f32) {                              \
+      constexpr int NWC = 2;                            \
+      using TC = double;                                \
+      KERNEL_CALL;                                      \
+    } else if (nw == 2) {                               \
+      constexpr int NWC = 2;                            \
+      using TC = float;                                 \
+      KERNEL_CALL;                                      \
+    } else if (!f32) {                                  \
+      constexpr int NWC = 4;                            \
+      using TC = double;                                \
+      KERNEL_CALL;                                      \
+    } else {                                            \
+      constexpr int NWC = 4;                            \
+      using TC = float;                                 \
+      KERNEL_CALL;                                      \
+    }                                                   \
+  } while (0)
+
+}  // namespace itpp

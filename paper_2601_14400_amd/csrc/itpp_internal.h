@@ -169,7 +169,8 @@ struct SelBuf {
   uint64_t cap;         // capacity of each array in elements
 };
 
-// Host launchers (defined in itpp_kernels.hip).
+// Host launchers (gate and partition in itpp_gate.hip, the others in
+// itpp_kernels.hip).
 hipError_t launch_init(int nw, int f32, Side s0, Plan* plan, Filter* filt, Ctl* ctl, int w0, hipStream_t st);
 hipError_t launch_partition(int nw, const GateParams& gp, Side in, const Plan* plan_in, Ctl* ctl, uint64_t* part,
                             hipStream_t st);

@@ -99,6 +99,14 @@ def test_f32_massive_ties_h0():
     e.close()
 
 
+def test_f32_massive_ties_h0_large_groups():
+    w = W.tfim_workload("t", 16, 1.0, 0.0, False, 1, 0.1, 0.6, 0.0, 1500)
+    e, st, S = run_gpu(w)
+    ref, _ = OR.run_workload(w, precision="f32")
+    assert_same_state({k: float(v) for k, v in ref.items()}, S)
+    e.close()
+
+
 @pytest.mark.parametrize("margin", [1.0, 0.5])
 def test_f32_speculation_margin_does_not_change_results(margin):
     w = W.config3(K=3000)

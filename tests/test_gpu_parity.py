@@ -121,6 +121,18 @@ def test_massive_ties_h0():
     e.close()
 
 
+def test_massive_ties_h0_large_groups():
+    """h = 0, n = 16 open, K = 1500: the cap cuts groups of up to 1365 equal
+    values, more than the direct ranking of tied keys handles, so the radix
+    selection over canonical keys decides."""
+    w = W.tfim_workload("t", 16, 1.0, 0.0, False, 1, 0.1, 0.6, 0.0, 1500)
+    e, st, S = gpu_state(w)
+    ref, _ = OR.run_workload(w)
+    assert_same_state(ref, S)
+    assert st["cap_hit"] == 1
+    e.close()
+
+
 def test_cap_one_keeps_identity():
     w = W.tfim_workload("t", 8, 1.0, 1.0, True, 1, 0.05, 0.2, 1e-14, 1)
     e, st, S = gpu_state(w)
