@@ -132,14 +132,21 @@ def strings_to_words(strings: Sequence[str], n: int) -> Tuple[np.ndarray, np.nda
 
 
 def words_to_strings(x: np.ndarray, z: np.ndarray, n: int) -> List[str]:
-    out = []
-    for s in range(x.shape[0]):
-        letters = []
-        for j in range(n):
-            xb = (int(x[s, j >> 6]) >> (j & 63)) & 1
-            zb = (int(z[s, j >> 6]) >> (j & 63)) & 1
-            letters.append("IXZY"[xb | (zb << 1)])
-        out.append("".join(letters))
+    """Unpack x/z words into 'IXYZ' strings (character j = qubit j)."""
+    out: List[str] = []
+    if n <= 0:
+        return [""] * x.shape[0]
+    j = np.arange(n)
+    word = j >> 6
+    shift = (j & 63).astype(np.uint64)
+    lut = np.frombuffer(b"IXZY", dtype=np.uint8)
+    one = np.uint64(1)
+    for r0 in range(0, x.shape[0], 1 << 16):
+        xs = np.asarray(x[r0:r0 + (1 << 16)], dtype=np.uint64)
+        zs = np.asarray(z[r0:r0 + (1 << 16)], dtype=np.uint64)
+        code = ((xs[:, word] >> shift) & one) | (((zs[:, word] >> shift) & one) << one)
+        chars = np.ascontiguousarray(lut[code.astype(np.uint8)])
+        out.extend(b.decode("ascii") for b in chars.view(f"S{n}").ravel())
     return out
 
 
