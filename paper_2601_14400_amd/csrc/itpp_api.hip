@@ -139,6 +139,23 @@ itpp_status hip_fail(itpp_ctx c, hipError_t e, const char* where) {
     if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
   } while (0)
 
+// Device memory owned by one API call; freed on every return path (hipFree
+// waits for the work still using it).
+struct DevBuf {
+  void* p = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes); }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
 void move_top(std::vector<int>& pos, int cb, int nbits, int* old_pos) {
   const int p = pos[cb];
   if (old_pos) *old_pos = p;
@@ -862,26 +879,22 @@ itpp_status itpp_expect(itpp_ctx c, int32_t m, const uint64_t* x, const uint64_t
     *out = 0.0;
     return ITPP_OK;
   }
-  uint64_t *dx = nullptr, *dz = nullptr;
-  double* dc = nullptr;
-  HIP_TRY(c, hipMalloc(&dx, sizeof(uint64_t) * m * W));
-  HIP_TRY(c, hipMalloc(&dz, sizeof(uint64_t) * m * W));
-  HIP_TRY(c, hipMalloc(&dc, sizeof(double) * m));
-  hipMemcpyAsync(dx, x, sizeof(uint64_t) * m * W, hipMemcpyHostToDevice, c->stream);
-  hipMemcpyAsync(dz, z, sizeof(uint64_t) * m * W, hipMemcpyHostToDevice, c->stream);
-  hipMemcpyAsync(dc, coef, sizeof(double) * m, hipMemcpyHostToDevice, c->stream);
+  double r = 0.0;  // outlives the device buffers, whose release waits for the copy into it
+  DevBuf bx, bz, bc;
+  HIP_TRY(c, bx.alloc(sizeof(uint64_t) * m * W));
+  HIP_TRY(c, bz.alloc(sizeof(uint64_t) * m * W));
+  HIP_TRY(c, bc.alloc(sizeof(double) * m));
+  HIP_TRY(c, hipMemcpyAsync(bx.p, x, sizeof(uint64_t) * m * W, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(bz.p, z, sizeof(uint64_t) * m * W, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(bc.p, coef, sizeof(double) * m, hipMemcpyHostToDevice, c->stream));
   RepPos rp{};
   rp.nbits = c->nbits;
   for (int b = 0; b < c->nbits; ++b) rp.pos[b] = (uint8_t)c->pos[b];
-  hipError_t e = launch_observe(c->NW, c->f32, c->side[c->cur], c->plan + c->par, c->filt + c->par, rp, dx, dz, dc, m,
-                                c->d_result, c->ctl, c->stream);
-  double r = 0.0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&r, c->d_result, sizeof(double), hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  (void)hipFree(dx);
-  (void)hipFree(dz);
-  (void)hipFree(dc);
-  if (e != hipSuccess) return hip_fail(c, e, "itpp_expect");
+  HIP_TRY(c, launch_observe(c->NW, c->f32, c->side[c->cur], c->plan + c->par, c->filt + c->par, rp,
+                            bx.as<uint64_t>(), bz.as<uint64_t>(), bc.as<double>(), m, c->d_result, c->ctl,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(&r, c->d_result, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   *out = r;
   return ITPP_OK;
 }
@@ -897,32 +910,30 @@ itpp_status itpp_export(itpp_ctx c, int64_t capacity, uint64_t* x, uint64_t* z, 
     return fail(c, ITPP_ERR_ARG, "export capacity too small");
   }
   const int W = c->W;
-  uint64_t *dx = nullptr, *dz = nullptr;
-  double* dc = nullptr;
-  unsigned long long* dn = nullptr;
-  HIP_TRY(c, hipMalloc(&dx, sizeof(uint64_t) * std::max<int64_t>(nt, 1) * W));
-  HIP_TRY(c, hipMalloc(&dz, sizeof(uint64_t) * std::max<int64_t>(nt, 1) * W));
-  HIP_TRY(c, hipMalloc(&dc, sizeof(double) * std::max<int64_t>(nt, 1)));
-  HIP_TRY(c, hipMalloc(&dn, sizeof(unsigned long long)));
-  hipMemsetAsync(dn, 0, sizeof(unsigned long long), c->stream);
-  RepPos rp{};
-  rp.nbits = c->nbits;
-  for (int b = 0; b < c->nbits; ++b) rp.pos[b] = (uint8_t)c->pos[b];
-  hipError_t e = launch_export(c->NW, c->f32, c->side[c->cur], c->plan + c->par, c->filt + c->par, rp, dx, dz, dc, dn,
-                               (uint64_t)nt, c->cus * 4, c->stream);
+  // host buffers first: they must outlive the device buffers, whose release
+  // waits for copies still in flight into them
   unsigned long long cnt = 0;
   std::vector<uint64_t> hx((size_t)nt * W), hz((size_t)nt * W);
   std::vector<double> hc(nt);
-  if (e == hipSuccess) e = hipMemcpyAsync(&cnt, dn, sizeof(cnt), hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess && nt > 0) e = hipMemcpyAsync(hx.data(), dx, sizeof(uint64_t) * nt * W, hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess && nt > 0) e = hipMemcpyAsync(hz.data(), dz, sizeof(uint64_t) * nt * W, hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess && nt > 0) e = hipMemcpyAsync(hc.data(), dc, sizeof(double) * nt, hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  (void)hipFree(dx);
-  (void)hipFree(dz);
-  (void)hipFree(dc);
-  (void)hipFree(dn);
-  if (e != hipSuccess) return hip_fail(c, e, "itpp_export");
+  DevBuf bx, bz, bc, bn;
+  HIP_TRY(c, bx.alloc(sizeof(uint64_t) * std::max<int64_t>(nt, 1) * W));
+  HIP_TRY(c, bz.alloc(sizeof(uint64_t) * std::max<int64_t>(nt, 1) * W));
+  HIP_TRY(c, bc.alloc(sizeof(double) * std::max<int64_t>(nt, 1)));
+  HIP_TRY(c, bn.alloc(sizeof(unsigned long long)));
+  HIP_TRY(c, hipMemsetAsync(bn.p, 0, sizeof(unsigned long long), c->stream));
+  RepPos rp{};
+  rp.nbits = c->nbits;
+  for (int b = 0; b < c->nbits; ++b) rp.pos[b] = (uint8_t)c->pos[b];
+  HIP_TRY(c, launch_export(c->NW, c->f32, c->side[c->cur], c->plan + c->par, c->filt + c->par, rp,
+                           bx.as<uint64_t>(), bz.as<uint64_t>(), bc.as<double>(), bn.as<unsigned long long>(),
+                           (uint64_t)nt, c->cus * 4, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(&cnt, bn.p, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+  if (nt > 0) {
+    HIP_TRY(c, hipMemcpyAsync(hx.data(), bx.p, sizeof(uint64_t) * nt * W, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(hz.data(), bz.p, sizeof(uint64_t) * nt * W, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(hc.data(), bc.p, sizeof(double) * nt, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   if ((int64_t)cnt != nt) return fail(c, ITPP_ERR_DEVICE, "internal error: export count mismatch");
   std::vector<int64_t> order(nt);
   for (int64_t i = 0; i < nt; ++i) order[i] = i;
@@ -1192,17 +1203,20 @@ itpp_status itpp_backward(itpp_ctx c, int32_t m, const uint64_t* x, const uint64
     ar.size = want;
     ok = ar.base != nullptr;
   }
+  hipError_t ce = hipSuccess;
   if (ok && m > 0) {
-    ok = hipMemcpyAsync(dx, x, sizeof(uint64_t) * m * W, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
-         hipMemcpyAsync(dz, z, sizeof(uint64_t) * m * W, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
-         hipMemcpyAsync(dc, coef, sizeof(double) * m, hipMemcpyHostToDevice, c->stream) == hipSuccess;
+    ce = hipMemcpyAsync(dx, x, sizeof(uint64_t) * m * W, hipMemcpyHostToDevice, c->stream);
+    if (ce == hipSuccess) ce = hipMemcpyAsync(dz, z, sizeof(uint64_t) * m * W, hipMemcpyHostToDevice, c->stream);
+    if (ce == hipSuccess) ce = hipMemcpyAsync(dc, coef, sizeof(double) * m, hipMemcpyHostToDevice, c->stream);
   }
-  if (ok) {
+  if (!ok) {
+    st = fail(c, ITPP_ERR_OOM, "device memory for the reverse sweep is not available");
+  } else if (ce != hipSuccess) {
+    st = hip_fail(c, ce, "copy of the observable to the device");
+  } else {
     double v = 0.0;
     st = backward_impl(c, m, dx, dz, dc, &v, d_alpha, d_dtau, d_theta, ar, B);
     if (st == ITPP_OK) *value = v;
-  } else {
-    st = fail(c, ITPP_ERR_OOM, "device memory for the reverse sweep is not available");
   }
   (void)hipStreamSynchronize(c->stream);
   for (void* p : mem) (void)hipFree(p);
