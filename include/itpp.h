@@ -129,6 +129,27 @@ itpp_status itpp_set_schedule(itpp_ctx ctx, int32_t n_gates, const int32_t* term
 /* Reset the state to rho = I (a single identity string with coefficient 1). */
 itpp_status itpp_reset(itpp_ctx ctx);
 
+/* Replace the state by rho proportional to sum_j coef[j] P_j (the Pauli-basis
+ * expansion of Sec. II.B, Eq. Observable_Pauli) and restart the schedule at
+ * its first gate.
+ * x, z: n_strings * W canonical words each, in the layout itpp_export writes;
+ * coef: n_strings values.  Host arrays, copied during the call.
+ * - The identity must be present with a coefficient above max(0, threshold).
+ *   The state is normalised by it (Sec. II.C): itpp_export then returns
+ *   coef[j] / coef[identity].
+ * - Other strings with |coef| at or below the threshold are dropped (every
+ *   stored value exceeds it, Sec. II.B).  At most max_terms strings may remain.
+ * - Strings must be distinct, with no bits at or above n_qubits; coefficients
+ *   must be finite.  An ITPP_F32 context rounds them to binary32 first (the
+ *   threshold and identity tests then apply to the rounded values).
+ * - Needs a schedule: the stored layout depends on its first two gates.  A
+ *   later itpp_set_hamiltonian or itpp_set_schedule returns to rho = I.
+ * ITPP_ERR_ARG on bad input (the previous state is kept), ITPP_ERR_STATE
+ * without a schedule, ITPP_ERR_DEVICE on a HIP error (then no valid state
+ * remains until itpp_reset). */
+itpp_status itpp_import(itpp_ctx ctx, int64_t n_strings, const uint64_t* x, const uint64_t* z,
+                        const double* coef);
+
 /* Apply n_steps Trotter steps of the schedule with step dtau > 0 (finite).
  * Runs asynchronously on cfg.stream except for the final status check; st
  * (nullable) receives the statistics of this call.  ITPP_ERR_CAP under

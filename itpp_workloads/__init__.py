@@ -297,3 +297,75 @@ def random_two_flip_workload(name: str, n: int, n_terms: int, seed: int, dtau: f
     return Workload(name=name, n=n, strings=strings, alphas=alphas, schedule=sched, dtau=dtau,
                     n_steps=n_steps, delta=delta, K=K, observables={"energy": (list(strings), list(alphas))},
                     meta=dict(model="random_two_flip", seed=seed))
+
+
+# ---------------------------------------------------------------------------
+# Synthetic states (inputs for loading a state directly, e.g. at full size).
+# ---------------------------------------------------------------------------
+
+def string_words(P: str) -> Tuple[np.ndarray, np.ndarray]:
+    """Canonical x/z words of one string (qubit j -> bit j of word j // 64;
+    X and Y set the x bit, Z and Y the z bit)."""
+    n = len(P)
+    W = (n + 63) // 64
+    x = np.zeros(W, dtype=np.uint64)
+    z = np.zeros(W, dtype=np.uint64)
+    for j, a in enumerate(P):
+        bit = np.uint64(1) << np.uint64(j & 63)
+        if a in "XY":
+            x[j >> 6] |= bit
+        if a in "ZY":
+            z[j >> 6] |= bit
+    return x, z
+
+
+def synthetic_state_words(n: int, count: int, seed: int, partner: Optional[str] = None,
+                          partner_frac: float = 0.3, levels: int = 76,
+                          step: float = 0.25) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """A seeded state of ``count`` distinct strings on ``n`` qubits as canonical
+    words ``x, z`` (shape ``(count, W)``) and coefficients.
+
+    * Row 0 is the identity with coefficient 1.
+    * The other strings are uniformly random; about ``partner_frac`` of them
+      also appear flipped by ``partner``'s bits (so a gate with that string
+      meets partner pairs).
+    * Magnitudes are ``2**(-k*step)`` for integer ``k`` uniform in
+      ``[1, levels]`` with random signs: a few dozen distinct values, so a cap
+      cuts through large groups of equal magnitudes.
+    """
+    if count < 1:
+        raise ValueError("count must be >= 1")
+    rng = np.random.default_rng(seed)
+    W = (n + 63) // 64
+    masks = np.array([np.uint64((1 << min(64, n - 64 * q)) - 1) if n - 64 * q < 64 else np.uint64(0xFFFFFFFFFFFFFFFF)
+                      for q in range(W)], dtype=np.uint64)
+    m = count - 1
+    # a margin over the expected count; the surplus is cut after removing repeats
+    base = int(1.05 * m / (1.0 + partner_frac)) + 64 if partner is not None else m + 64
+    xs = rng.integers(0, 2**63, size=(base, W), dtype=np.uint64) * np.uint64(2) + \
+        rng.integers(0, 2, size=(base, W), dtype=np.uint64)
+    zs = rng.integers(0, 2**63, size=(base, W), dtype=np.uint64) * np.uint64(2) + \
+        rng.integers(0, 2, size=(base, W), dtype=np.uint64)
+    xs &= masks
+    zs &= masks
+    if partner is not None:
+        qx, qz = string_words(partner)
+        pick = rng.random(base) < partner_frac
+        xs = np.concatenate([xs, xs[pick] ^ qx])
+        zs = np.concatenate([zs, zs[pick] ^ qz])
+    # distinct, non-identity, in random order, exactly m of them
+    rows = np.concatenate([xs, zs], axis=1)
+    rows = rows[np.any(rows != 0, axis=1)]
+    order = np.lexsort(tuple(rows[:, i] for i in reversed(range(rows.shape[1]))))  # stable
+    srt = rows[order]
+    repeat = np.concatenate([[False], np.all(srt[1:] == srt[:-1], axis=1)])
+    rows = rows[np.sort(order[~repeat])]
+    if rows.shape[0] < m:
+        raise ValueError("not enough distinct strings; lower partner_frac or raise n")
+    rows = rows[rng.permutation(rows.shape[0])[:m]]
+    x = np.concatenate([np.zeros((1, W), dtype=np.uint64), rows[:, :W]])
+    z = np.concatenate([np.zeros((1, W), dtype=np.uint64), rows[:, W:]])
+    k = rng.integers(1, levels + 1, size=m)
+    sign = np.where(rng.random(m) < 0.5, -1.0, 1.0)
+    coef = np.concatenate([[1.0], sign * np.exp2(-step * k.astype(np.float64))])
+    return x, z, coef

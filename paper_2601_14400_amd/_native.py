@@ -21,7 +21,7 @@ STATUS = {0: "ITPP_OK", 1: "ITPP_ERR_ARG", 2: "ITPP_ERR_OOM", 3: "ITPP_ERR_CAP",
 
 # Every entry point declared in include/itpp.h.
 EXPORTED = ["itpp_create", "itpp_destroy", "itpp_set_hamiltonian", "itpp_set_schedule",
-            "itpp_reset", "itpp_evolve", "itpp_evolve_gates", "itpp_expect", "itpp_num_terms", "itpp_export",
+            "itpp_reset", "itpp_import", "itpp_evolve", "itpp_evolve_gates", "itpp_expect", "itpp_num_terms", "itpp_export",
             "itpp_set_adjoint", "itpp_backward", "itpp_set_option", "itpp_set_timing", "itpp_get_timing",
             "itpp_batch_create", "itpp_batch_destroy", "itpp_batch_instance", "itpp_batch_set_workers",
             "itpp_batch_evolve", "itpp_batch_autotune", "itpp_batch_last_error",
@@ -79,6 +79,7 @@ def load_library(path: Optional[str] = None):
     lib.itpp_set_hamiltonian.argtypes = [vp, i32, vp, vp, vp]
     lib.itpp_set_schedule.argtypes = [vp, i32, vp, vp]
     lib.itpp_reset.argtypes = [vp]
+    lib.itpp_import.argtypes = [vp, i64, vp, vp, vp]
     lib.itpp_evolve.argtypes = [vp, dbl, i64, ctypes.POINTER(ItppStats)]
     lib.itpp_evolve_gates.argtypes = [vp, dbl, i64, ctypes.POINTER(ItppStats)]
     lib.itpp_expect.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(dbl)]
@@ -233,6 +234,23 @@ class Engine:
     def reset(self):
         self._check(self._lib.itpp_reset(self._h))
         self.gates_since_reset = 0
+
+    def import_words(self, x: np.ndarray, z: np.ndarray, coef: np.ndarray):
+        """Replace the state by sum_j coef[j] P_j (canonical x/z words, the
+        layout export() returns); normalised by the identity's coefficient."""
+        x = np.ascontiguousarray(x, dtype=np.uint64).reshape(-1, self.W)
+        z = np.ascontiguousarray(z, dtype=np.uint64).reshape(-1, self.W)
+        coef = np.ascontiguousarray(coef, dtype=np.float64).reshape(-1)
+        if not (x.shape[0] == z.shape[0] == coef.shape[0]):
+            raise ValueError("x, z and coef must describe the same number of strings")
+        self._check(self._lib.itpp_import(self._h, ctypes.c_int64(coef.shape[0]), x.ctypes.data, z.ctypes.data,
+                                          coef.ctypes.data))
+
+    def load(self, S: Dict[str, float]):
+        """Replace the state by the strings and coefficients of S."""
+        keys = list(S)
+        x, z = strings_to_words(keys, self.n)
+        self.import_words(x, z, np.array([S[k] for k in keys], dtype=np.float64))
 
     def evolve(self, dtau: float, n_steps: int) -> Dict[str, float]:
         st = ItppStats()

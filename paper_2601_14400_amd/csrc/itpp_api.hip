@@ -302,14 +302,16 @@ hipError_t restore_snapshot(itpp_ctx c, const Snapshot& s) {
 }
 
 // Initial rep: identity permutation with the first gate's flip bits on top.
-void reset_rep(itpp_ctx c) {
-  c->pos.resize(c->nbits);
-  for (int i = 0; i < c->nbits; ++i) c->pos[i] = i;
+void initial_rep(itpp_ctx c, std::vector<int>& pos) {
+  pos.resize(c->nbits);
+  for (int i = 0; i < c->nbits; ++i) pos[i] = i;
   if (!c->glist.empty()) {
     const TermInfo& t = c->terms[c->sched_term[c->glist[0]]];
-    for (int b : t.F) move_top(c->pos, b, c->nbits, nullptr);
+    for (int b : t.F) move_top(pos, b, c->nbits, nullptr);
   }
 }
+
+void reset_rep(itpp_ctx c) { initial_rep(c, c->pos); }
 
 itpp_status do_reset(itpp_ctx c) {
   reset_rep(c);
@@ -570,6 +572,133 @@ itpp_status itpp_set_schedule(itpp_ctx c, int32_t n_gates, const int32_t* term_i
 itpp_status itpp_reset(itpp_ctx c) {
   if (!c) return ITPP_ERR_ARG;
   return do_reset(c);
+}
+
+itpp_status itpp_import(itpp_ctx c, int64_t m, const uint64_t* x, const uint64_t* z, const double* coef) {
+  if (!c) return ITPP_ERR_ARG;
+  if (m < 1 || !x || !z || !coef) return fail(c, ITPP_ERR_ARG, "empty state");
+  if (c->glist.empty()) return fail(c, ITPP_ERR_STATE, "set_hamiltonian and set_schedule first");
+  const int W = c->W, NW = c->NW, n = c->n, nbits = c->nbits;
+  const double delta = c->cfg.threshold;
+  int64_t ident = -1;
+  for (int64_t j = 0; j < m; ++j) {
+    uint64_t any = 0;
+    for (int q = 0; q < W; ++q) {
+      const uint64_t xw = x[(size_t)j * W + q], zw = z[(size_t)j * W + q];
+      any |= xw | zw;
+      const int hi = n - 64 * q;
+      if (hi < 64) {
+        const uint64_t bad = hi <= 0 ? ~0ull : ~((1ull << hi) - 1ull);
+        if ((xw | zw) & bad) return fail(c, ITPP_ERR_ARG, "string has bits at or above n_qubits");
+      }
+    }
+    if (!std::isfinite(coef[j])) return fail(c, ITPP_ERR_ARG, "non-finite coefficient");
+    if (any == 0) {
+      if (ident >= 0) return fail(c, ITPP_ERR_ARG, "duplicate string (identity)");
+      ident = j;
+    }
+  }
+  if (ident < 0) return fail(c, ITPP_ERR_ARG, "the identity string is missing");
+  // the context's precision decides the stored value and the threshold test
+  auto stored = [&](int64_t j) { return c->f32 ? (double)(float)coef[j] : coef[j]; };
+  const double cI = stored(ident);
+  if (!(cI > 0.0) || !(cI > delta)) return fail(c, ITPP_ERR_ARG, "identity coefficient must exceed max(0, threshold)");
+  // layout of the state after a reset: rep with the first gate's flip bits on
+  // top, one producer class, region e = class under the first gate, sorted
+  std::vector<int> pos;
+  initial_rep(c, pos);
+  const int G = (int)c->glist.size();
+  const TermInfo& t0 = c->terms[c->sched_term[c->glist[0]]];
+  const TermInfo& t1 = c->terms[c->sched_term[c->glist[1 % G]]];
+  const int w0 = (int)t0.F.size();
+  std::vector<int64_t> keep;
+  keep.reserve((size_t)m);
+  for (int64_t j = 0; j < m; ++j)
+    if (j == ident || std::fabs(stored(j)) > delta) keep.push_back(j);
+  const int64_t N = (int64_t)keep.size();
+  if (N > c->cfg.max_terms || (uint64_t)N > c->cap)
+    return fail(c, ITPP_ERR_ARG, "more strings above the threshold than max_terms");
+  std::vector<uint64_t> rk((size_t)N * NW, 0ull);
+  for (int64_t k = 0; k < N; ++k) {
+    const int64_t j = keep[k];
+    uint64_t* key = &rk[(size_t)k * NW];
+    for (int q = 0; q < W; ++q)
+      for (int part = 0; part < 2; ++part) {
+        uint64_t wv = part == 0 ? x[(size_t)j * W + q] : z[(size_t)j * W + q];
+        while (wv) {
+          const int b = __builtin_ctzll(wv);
+          wv &= wv - 1;
+          const int p = pos[part * n + 64 * q + b];
+          key[p >> 6] |= 1ull << (p & 63);
+        }
+      }
+  }
+  auto key_lt = [&](int64_t a, int64_t b) {
+    for (int q = NW - 1; q >= 0; --q) {
+      const uint64_t ka = rk[(size_t)a * NW + q], kb = rk[(size_t)b * NW + q];
+      if (ka != kb) return ka < kb;
+    }
+    return false;
+  };
+  std::vector<int64_t> order((size_t)N);
+  for (int64_t k = 0; k < N; ++k) order[k] = k;
+  std::sort(order.begin(), order.end(), key_lt);
+  auto rbit = [&](int64_t k, int p) { return (int)((rk[(size_t)k * NW + (p >> 6)] >> (p & 63)) & 1ull); };
+  Plan pl{};
+  pl.wc = 0;
+  pl.we = w0;
+  // host copies are declared before anything is enqueued and outlive the
+  // stream synchronisation below
+  std::vector<std::vector<uint64_t>> hk(NW, std::vector<uint64_t>((size_t)N));
+  std::vector<double> hc64(c->f32 ? 0 : (size_t)N);
+  std::vector<float> hc32(c->f32 ? (size_t)N : 0);
+  for (int64_t r = 0; r < N; ++r) {
+    const int64_t k = order[r];
+    if (r > 0 && !key_lt(order[r - 1], k)) return fail(c, ITPP_ERR_ARG, "duplicate string");
+    int e = 0, f = 0;
+    for (int b = 0; b < w0; ++b) e |= rbit(k, nbits - w0 + b) << b;
+    for (int b = 0; b < (int)t1.F.size(); ++b) f |= rbit(k, pos[t1.F[b]]) << b;
+    pl.cnt[0][e] += 1;
+    pl.ncnt[e][f] += 1;
+    for (int q = 0; q < NW; ++q) hk[q][(size_t)r] = rk[(size_t)k * NW + q];
+    const double v = coef[keep[k]];
+    if (c->f32)
+      hc32[(size_t)r] = (float)v;
+    else
+      hc64[(size_t)r] = v;
+  }
+  uint64_t acc = 0;
+  for (int e = 0; e < kMaxClasses; ++e) {
+    pl.base[0][e] = acc;
+    acc += pl.cnt[0][e];
+  }
+  Filter fl{};
+  fl.cI = cI;
+  fl.n_written = (uint64_t)N;
+  fl.n_survivors = (uint64_t)N;
+  // from here on a failure leaves no valid state
+  c->ready = false;
+  free_ckpts(c);
+  HIP_TRY(c, launch_init(c->NW, c->f32, c->side[0], c->plan + 0, c->filt + 0, c->ctl, w0, c->stream));
+  for (int q = 0; q < NW; ++q)
+    HIP_TRY(c, hipMemcpyAsync(c->side[0].kw[q], hk[q].data(), sizeof(uint64_t) * N, hipMemcpyHostToDevice,
+                              c->stream));
+  if (c->f32)
+    HIP_TRY(c, hipMemcpyAsync(c->side[0].coef, hc32.data(), sizeof(float) * N, hipMemcpyHostToDevice, c->stream));
+  else
+    HIP_TRY(c, hipMemcpyAsync(c->side[0].coef, hc64.data(), sizeof(double) * N, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->plan + 0, &pl, sizeof(Plan), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->filt + 0, &fl, sizeof(Filter), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->pos.swap(pos);
+  c->fwd_gates = 0;
+  c->fwd_dtau = 0.0;
+  c->fwd_valid = true;
+  c->cur = 0;
+  c->par = 0;
+  c->gpos = 0;
+  c->ready = true;
+  return ITPP_OK;
 }
 
 static itpp_status run_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stats* st);
