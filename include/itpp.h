@@ -181,6 +181,24 @@ itpp_status itpp_num_terms(itpp_ctx ctx, int64_t* out);
 itpp_status itpp_export(itpp_ctx ctx, int64_t capacity, uint64_t* x, uint64_t* z, double* coef,
                         int64_t* n_out);
 
+/* Device-pointer variants, for arrays that already live on the device (for
+ * example torch tensors).  Both run on cfg.stream; the arrays must be ready
+ * on that stream and stay valid until the work is done.
+ *
+ * itpp_expect_device: as itpp_expect with x, z, coef and out in device
+ * memory.  Enqueued without waiting: out holds <O> once cfg.stream reaches
+ * this point.  Bits at or above n_qubits cannot be checked and are ignored.
+ *
+ * itpp_export_device: the surviving strings (canonical words, normalised
+ * coefficients as itpp_export) written to device arrays of at least
+ * capacity strings, in storage order (unspecified; itpp_export sorts them).
+ * Waits for the stream; n_out (host) receives the count, also when the
+ * capacity is too small (then ITPP_ERR_ARG and nothing is written). */
+itpp_status itpp_expect_device(itpp_ctx ctx, int32_t n_strings, const uint64_t* x, const uint64_t* z,
+                               const double* coef, double* out);
+itpp_status itpp_export_device(itpp_ctx ctx, int64_t capacity, uint64_t* x, uint64_t* z, double* coef,
+                               int64_t* n_out);
+
 /* Reverse sweep (derivatives of an observable with the truncation support
  * held fixed).  The forward map of Algorithm 1 is differentiated gate by
  * gate: for the division by the identity coefficient b_I,

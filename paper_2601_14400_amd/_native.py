@@ -22,6 +22,7 @@ STATUS = {0: "ITPP_OK", 1: "ITPP_ERR_ARG", 2: "ITPP_ERR_OOM", 3: "ITPP_ERR_CAP",
 # Every entry point declared in include/itpp.h.
 EXPORTED = ["itpp_create", "itpp_destroy", "itpp_set_hamiltonian", "itpp_set_schedule",
             "itpp_reset", "itpp_import", "itpp_evolve", "itpp_evolve_gates", "itpp_expect", "itpp_num_terms", "itpp_export",
+            "itpp_expect_device", "itpp_export_device",
             "itpp_set_adjoint", "itpp_backward", "itpp_set_option", "itpp_set_timing", "itpp_get_timing",
             "itpp_batch_create", "itpp_batch_destroy", "itpp_batch_instance", "itpp_batch_set_workers",
             "itpp_batch_evolve", "itpp_batch_autotune", "itpp_batch_last_error",
@@ -85,6 +86,8 @@ def load_library(path: Optional[str] = None):
     lib.itpp_expect.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(dbl)]
     lib.itpp_num_terms.argtypes = [vp, ctypes.POINTER(i64)]
     lib.itpp_export.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(i64)]
+    lib.itpp_expect_device.argtypes = [vp, i32, vp, vp, vp, vp]
+    lib.itpp_export_device.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(i64)]
     lib.itpp_set_adjoint.argtypes = [vp, i32, i64]
     lib.itpp_backward.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(dbl), vp, ctypes.POINTER(dbl), vp]
     lib.itpp_set_option.argtypes = [vp, i32, dbl]
@@ -325,6 +328,45 @@ class Engine:
         n_out = ctypes.c_int64()
         self._check(self._lib.itpp_export(self._h, m, x.ctypes.data, z.ctypes.data, c.ctypes.data,
                                           ctypes.byref(n_out)))
+        k = int(n_out.value)
+        return x[:k], z[:k], c[:k]
+
+    def expect_device(self, x, z, coef, out=None):
+        """<O> for observables held in torch device tensors: x, z int64 (the
+        bit patterns of the canonical words, shape (m, W)), coef float64 (m,).
+        Enqueued on the engine's stream (the torch stream current when the
+        engine was created); returns a 0-dim float64 device tensor."""
+        import torch
+
+        x = x.contiguous()
+        z = z.contiguous()
+        coef = coef.contiguous()
+        m = coef.shape[0]
+        for t, dt in ((x, torch.int64), (z, torch.int64), (coef, torch.float64)):
+            if t.dtype != dt or not t.is_cuda:
+                raise ValueError("expect_device takes int64 x, z and float64 coef device tensors")
+        if x.shape != (m, self.W) or z.shape != (m, self.W):
+            raise ValueError(f"x and z must have shape ({m}, {self.W})")
+        if out is None:
+            out = torch.empty((), dtype=torch.float64, device=coef.device)
+        self._check(self._lib.itpp_expect_device(self._h, m, x.data_ptr(), z.data_ptr(), coef.data_ptr(),
+                                                 out.data_ptr()))
+        return out
+
+    def export_device(self):
+        """The surviving strings as torch device tensors (x, z int64 bit
+        patterns of shape (m, W), normalised float64 coefficients), in storage
+        order."""
+        import torch
+
+        m = self.num_terms()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        x = torch.empty((max(m, 1), self.W), dtype=torch.int64, device=dev)
+        z = torch.empty((max(m, 1), self.W), dtype=torch.int64, device=dev)
+        c = torch.empty((max(m, 1),), dtype=torch.float64, device=dev)
+        n_out = ctypes.c_int64()
+        self._check(self._lib.itpp_export_device(self._h, m, x.data_ptr(), z.data_ptr(), c.data_ptr(),
+                                                 ctypes.byref(n_out)))
         k = int(n_out.value)
         return x[:k], z[:k], c[:k]
 

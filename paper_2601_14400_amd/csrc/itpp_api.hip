@@ -76,6 +76,7 @@ struct itpp_ctx_s {
   uint64_t* part = nullptr;  // merge-path boundaries (2 words each)
   SelBuf sel{};
   double* d_result = nullptr;
+  unsigned long long* d_count = nullptr;  // strings written by itpp_export_device
   std::vector<void*> allocs;
   // model
   std::vector<TermInfo> terms;
@@ -448,6 +449,7 @@ itpp_status create_impl(const itpp_config* cfg, int dev, const hipDeviceProp_t& 
   if (ok) ok = dalloc(c, &c->sel.cand_idx, sel_cap) == hipSuccess;
   if (ok) ok = dalloc(c, &c->sel.tie_keys, sel_cap * c->NW) == hipSuccess;
   if (ok) ok = dalloc(c, &c->d_result, 4) == hipSuccess;
+  if (ok) ok = dalloc(c, &c->d_count, 1) == hipSuccess;
   if (measured) {
     *measured = c->arena_top;
     delete c;
@@ -1080,6 +1082,44 @@ itpp_status itpp_export(itpp_ctx c, int64_t capacity, uint64_t* x, uint64_t* z, 
     }
     coef[i] = hc[order[i]];
   }
+  *n_out = nt;
+  return ITPP_OK;
+}
+
+itpp_status itpp_expect_device(itpp_ctx c, int32_t m, const uint64_t* x, const uint64_t* z, const double* coef,
+                               double* out) {
+  if (!c || !out) return ITPP_ERR_ARG;
+  if (m < 0 || (m > 0 && (!x || !z || !coef))) return fail(c, ITPP_ERR_ARG, "bad observable arrays");
+  if (!c->ready) return fail(c, ITPP_ERR_STATE, "no valid state (reset required)");
+  RepPos rp{};
+  rp.nbits = c->nbits;
+  for (int b = 0; b < c->nbits; ++b) rp.pos[b] = (uint8_t)c->pos[b];
+  HIP_TRY(c, launch_observe(c->NW, c->f32, c->side[c->cur], c->plan + c->par, c->filt + c->par, rp, x, z, coef, m,
+                            out, c->ctl, c->stream));
+  return ITPP_OK;
+}
+
+itpp_status itpp_export_device(itpp_ctx c, int64_t capacity, uint64_t* x, uint64_t* z, double* coef,
+                               int64_t* n_out) {
+  if (!c || !n_out) return ITPP_ERR_ARG;
+  if (!c->ready) return fail(c, ITPP_ERR_STATE, "no valid state (reset required)");
+  int64_t nt = 0;
+  itpp_status s = itpp_num_terms(c, &nt);
+  if (s != ITPP_OK) return s;
+  if (capacity < nt || !x || !z || !coef) {
+    *n_out = nt;
+    return fail(c, ITPP_ERR_ARG, "export capacity too small");
+  }
+  RepPos rp{};
+  rp.nbits = c->nbits;
+  for (int b = 0; b < c->nbits; ++b) rp.pos[b] = (uint8_t)c->pos[b];
+  unsigned long long cnt = 0;
+  HIP_TRY(c, hipMemsetAsync(c->d_count, 0, sizeof(unsigned long long), c->stream));
+  HIP_TRY(c, launch_export(c->NW, c->f32, c->side[c->cur], c->plan + c->par, c->filt + c->par, rp, x, z, coef,
+                           c->d_count, (uint64_t)nt, c->cus * 4, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(&cnt, c->d_count, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if ((int64_t)cnt != nt) return fail(c, ITPP_ERR_DEVICE, "internal error: export count mismatch");
   *n_out = nt;
   return ITPP_OK;
 }
