@@ -438,6 +438,9 @@ def main():
     if rec is not None and args.K == (1 << 24) and args.beta == 2.0:
         out["roofline"]["traffic"] = rec["bytes_per_launch"]
         out["roofline"]["traffic_over_alg"] = rec["bytes_per_launch"] / bytes_per_launch
+        # measured HBM bytes over this run's event-timed launch average
+        out["roofline"]["traffic_GBps"] = rec["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
+        out["roofline"]["traffic_frac"] = out["roofline"]["traffic_GBps"] / HBM_PEAK_GBS
     if args.calibration_copy:
         x = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
         y = torch.empty_like(x)
