@@ -22,7 +22,10 @@ FP64 form on the same GPU (one step = one whole run of its workload):
            seed 1), cap 2^20 each: one batch vs a loop of single runs;
   adjoint  n=64 periodic TFIM, beta 1.5, cap 2^24: forward with checkpoints
            every 10 Trotter steps plus the reverse sweep of <H>, vs the plain
-           forward; d<H>/dJ, d<H>/dh, d<H>/dbeta.
+           forward; d<H>/dJ, d<H>/dh, d<H>/dbeta;
+  squared  the benchmark chain at cap 2^20 after beta = 2: <H>/n and <Z0 Z1>
+           at 2 beta from the squared state (Tr[(O rho) rho] / Tr[rho^2]),
+           in stored strings x observable strings per second.
 """
 from __future__ import annotations
 
@@ -117,7 +120,7 @@ def parse():
     ap.add_argument("--beta", type=float, default=2.0, help="final inverse temperature (default 2)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form", choices=["fp64", "fp32", "batched", "adjoint"], default="fp64")
+    ap.add_argument("--form", choices=["fp64", "fp32", "batched", "adjoint", "squared"], default="fp64")
     ap.add_argument("--progress", action="store_true", help="print a line after every tenth of the Trotter steps")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="end with three 256 MiB device copies (the byte counters' calibration in a --pmc run)")
@@ -337,6 +340,77 @@ def run_form_adjoint(args):
     return line, w
 
 
+def run_form_squared(args):
+    """Squared-state observables (<O>_{2 beta} from the state at beta) on the
+    benchmark chain at a 2^20 cap, after the whole run to beta = 2."""
+    import torch
+
+    import itpp_workloads as W
+    import paper_2601_14400_amd as P
+
+    K = 1 << 20
+    w = W.config2(K=K)
+    e = P.engine_for(w)
+    st = e.evolve(w.dtau, w.n_steps)
+    torch.cuda.synchronize()
+    N = st["n_terms"]
+    progress(f"state at beta = 2: {N} strings")
+    obs = {k: w.observables[k] for k in ("energy_per_site", "Z0Z1")}
+    res = {}
+    for name, (strings, coefs) in obs.items():
+        best = None
+        for _ in range(3):
+            t0 = time.perf_counter()
+            val, pur = e.expect_squared(strings, coefs)
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        res[name] = {"value_at_2beta": val, "purity": pur, "strings": len(strings), "seconds": best,
+                     "value_at_beta": e.expect(strings, coefs)}
+        progress(f"{name}: {best * 1e3:.1f} ms")
+    e.close()
+    m = len(obs["energy_per_site"][0])
+    t = res["energy_per_site"]["seconds"]
+    elem = 16 * ((w.n + 63) // 64) + 8
+    alg = N * elem * (1 + m)
+    line = base_line(args, N * m / t, t * 1e3, "f64",
+                     {"workload": f"tfim_n64_open_strang_dtau0.02_beta2.0_delta1e-6_K{K}_squared_energy",
+                      "form": "squared", "n_qubits": w.n, "K": K, "stored_strings": N, "observable_strings": m})
+    line["metric"] = "squared_string_pairs_per_sec"
+    line["unit"] = "string-pairs/s"
+    line["roofline"] = {"bound": "hbm", "achieved": alg / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": alg / t / 1e9 / HBM_PEAK_GBS, "traffic": None, "kernel": "squared_kernel",
+                        "alg_bytes": alg}
+    line["form"] = res
+    return line, w
+
+
+def cpu_baseline_squared(w, budget_s: float):
+    """The oracle's squared-state energy on the C++ oracle's own state after
+    the first gates of the same workload, grown until the evaluation covers
+    about 8e4 string pairs per second of budget (the pure-Python oracle makes
+    about 1e5 pair evaluations per second)."""
+    from oracle import c_oracle
+    from oracle import squared as SQ
+
+    c_oracle.build(force=False)
+    strings, coefs = w.observables["energy_per_site"]
+    target = 8e4 * budget_s
+    o = c_oracle.COracle(w.n, w.precision)
+    gates = 0
+    while o.size() * len(strings) < target and gates < len(w.schedule) * w.n_steps:
+        k, mlt = w.schedule[gates % len(w.schedule)]
+        o.evolve(w.strings, w.alphas, [(k, mlt)], w.dtau, 1, w.delta, w.K)
+        gates += 1
+    S = o.state()
+    t0 = time.perf_counter()
+    SQ.squared_expectation(S, strings, coefs)
+    dt = time.perf_counter() - t0
+    return {"value": len(S) * len(strings) / dt, "unit": "string-pairs/s", "cores": 1, "kind": "oracle",
+            "sample": f"Python dict oracle, squared-state energy ({len(strings)} strings) on the C++ oracle's state "
+                      f"after the first {gates} gates of the same workload ({len(S)} strings) in {dt:.1f} s; "
+                      f"host {platform.processor() or platform.machine()}, os.cpu_count()={os.cpu_count()}"}
+
+
 def main():
     args = parse()
     if args.summarize_pmc:
@@ -351,10 +425,12 @@ def main():
 
     if args.form != "fp64":
         torch.cuda.set_device(0)
-        line, w = {"fp32": run_form_fp32, "batched": run_form_batched, "adjoint": run_form_adjoint}[args.form](args)
+        line, w = {"fp32": run_form_fp32, "batched": run_form_batched, "adjoint": run_form_adjoint,
+                   "squared": run_form_squared}[args.form](args)
         if not args.no_cpu_baseline:
             progress("cpu baseline")
-            line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+            base = cpu_baseline_squared if args.form == "squared" else cpu_baseline
+            line["cpu_baseline"] = base(w, args.cpu_seconds)
         print(json.dumps(line), flush=True)
         return
 

@@ -181,6 +181,18 @@ itpp_status itpp_num_terms(itpp_ctx ctx, int64_t* out);
 itpp_status itpp_export(itpp_ctx ctx, int64_t capacity, uint64_t* x, uint64_t* z, double* coef,
                         int64_t* n_out);
 
+/* Squared-state estimate of Sec. II.C: <O>_{2 tau} ~= Tr[(O rho) rho] /
+ * Tr[rho^2] for the current state rho (imaginary time tau), without forming
+ * rho^2.  With rho = 2^-n sum_P a_P P (a_I = 1) and O = sum_j coef[j] Q_j:
+ * *purity = sum_P a_P^2 (= 2^n Tr[rho^2], the l2 norm of the coefficients)
+ * and *value = (sum_j coef[j] sum_P a_P a_R s) / *purity, where Q_j P = s R
+ * for the strings P that commute with Q_j (s = +-1; the others cancel in
+ * pairs).  Strings in the same layout as itpp_expect; any weight.  Host
+ * arrays; waits for the stream.  Cost grows with n_strings times the number
+ * of stored strings (one binary search per commuting pair). */
+itpp_status itpp_expect_squared(itpp_ctx ctx, int32_t n_strings, const uint64_t* x, const uint64_t* z,
+                                const double* coef, double* value, double* purity);
+
 /* Device-pointer variants, for arrays that already live on the device (for
  * example torch tensors).  Both run on cfg.stream; the arrays must be ready
  * on that stream and stay valid until the work is done.

@@ -21,6 +21,7 @@
 
 #include "../../include/itpp.h"
 #include "itpp_internal.h"
+#include "itpp_readout.h"
 
 using namespace itpp;
 
@@ -1083,6 +1084,98 @@ itpp_status itpp_export(itpp_ctx c, int64_t capacity, uint64_t* x, uint64_t* z, 
     coef[i] = hc[order[i]];
   }
   *n_out = nt;
+  return ITPP_OK;
+}
+
+itpp_status itpp_expect_squared(itpp_ctx c, int32_t m, const uint64_t* x, const uint64_t* z, const double* coef,
+                                double* value, double* purity) {
+  if (!c || !value || !purity) return ITPP_ERR_ARG;
+  if (m < 0 || (m > 0 && (!x || !z || !coef))) return fail(c, ITPP_ERR_ARG, "bad observable arrays");
+  if (!c->ready) return fail(c, ITPP_ERR_STATE, "no valid state (reset required)");
+  const int W = c->W, NW = c->NW, n = c->n;
+  std::vector<uint64_t> qmask((size_t)std::max(m, 1) * NW, 0ull), cmask((size_t)std::max(m, 1) * NW, 0ull);
+  std::vector<int32_t> sup_off(m + 1, 0), sup_pos, sup_q, aq(std::max(m, 1), 0);
+  std::vector<double> oc(std::max(m, 1), 0.0);
+  auto set_rep = [&](std::vector<uint64_t>& v, int j, int cb) {
+    const int p = c->pos[cb];
+    v[(size_t)j * NW + (p >> 6)] |= 1ull << (p & 63);
+  };
+  for (int j = 0; j < m; ++j) {
+    if (!std::isfinite(coef[j])) return fail(c, ITPP_ERR_ARG, "non-finite observable weight");
+    for (int q = 0; q < W; ++q) {
+      const int hi = n - 64 * q;
+      if (hi < 64) {
+        const uint64_t bad = hi <= 0 ? ~0ull : ~((1ull << hi) - 1ull);
+        if ((x[(size_t)j * W + q] | z[(size_t)j * W + q]) & bad)
+          return fail(c, ITPP_ERR_ARG, "observable has bits at or above n_qubits");
+      }
+    }
+    for (int i = 0; i < n; ++i) {
+      const int xi = (int)((x[(size_t)j * W + (i >> 6)] >> (i & 63)) & 1ull);
+      const int zi = (int)((z[(size_t)j * W + (i >> 6)] >> (i & 63)) & 1ull);
+      if (!xi && !zi) continue;
+      if (xi) {
+        set_rep(qmask, j, i);
+        set_rep(cmask, j, n + i);  // x_Q z_P
+      }
+      if (zi) {
+        set_rep(qmask, j, n + i);
+        set_rep(cmask, j, i);  // z_Q x_P
+      }
+      sup_pos.push_back(c->pos[i]);
+      sup_pos.push_back(c->pos[n + i]);
+      sup_q.push_back(xi | (zi << 1));
+      aq[j] += xi & zi;
+    }
+    aq[j] &= 3;
+    sup_off[j + 1] = (int32_t)sup_q.size();
+    oc[j] = coef[j];
+  }
+  if (sup_q.empty()) {
+    sup_q.push_back(0);
+    sup_pos.assign(2, 0);
+  }
+  const int grid = c->cus * 4;
+  double res[2] = {0.0, 0.0};  // outlives the device buffers, whose release waits for the copy into it
+  DevBuf bq, bc, boff, bpos, bql, baq, bco, bpart, bout;
+  HIP_TRY(c, bq.alloc(sizeof(uint64_t) * qmask.size()));
+  HIP_TRY(c, bc.alloc(sizeof(uint64_t) * cmask.size()));
+  HIP_TRY(c, boff.alloc(sizeof(int32_t) * sup_off.size()));
+  HIP_TRY(c, bpos.alloc(sizeof(int32_t) * sup_pos.size()));
+  HIP_TRY(c, bql.alloc(sizeof(int32_t) * sup_q.size()));
+  HIP_TRY(c, baq.alloc(sizeof(int32_t) * aq.size()));
+  HIP_TRY(c, bco.alloc(sizeof(double) * oc.size()));
+  HIP_TRY(c, bpart.alloc(sizeof(double) * 4 * (size_t)grid));
+  HIP_TRY(c, bout.alloc(sizeof(double) * 2));
+  HIP_TRY(c, hipMemcpyAsync(bq.p, qmask.data(), sizeof(uint64_t) * qmask.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(bc.p, cmask.data(), sizeof(uint64_t) * cmask.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(boff.p, sup_off.data(), sizeof(int32_t) * sup_off.size(), hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(bpos.p, sup_pos.data(), sizeof(int32_t) * sup_pos.size(), hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(bql.p, sup_q.data(), sizeof(int32_t) * sup_q.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(baq.p, aq.data(), sizeof(int32_t) * aq.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(bco.p, oc.data(), sizeof(double) * oc.size(), hipMemcpyHostToDevice, c->stream));
+  SqObs ob{};
+  ob.m = m;
+  ob.qmask = bq.as<uint64_t>();
+  ob.cmask = bc.as<uint64_t>();
+  ob.sup_off = boff.as<int32_t>();
+  ob.sup_pos = bpos.as<int32_t>();
+  ob.sup_q = bql.as<int32_t>();
+  ob.aq = baq.as<int32_t>();
+  ob.coef = bco.as<double>();
+  RepPos rp{};
+  rp.nbits = c->nbits;
+  for (int b = 0; b < c->nbits; ++b) rp.pos[b] = (uint8_t)c->pos[b];
+  HIP_TRY(c, launch_squared(c->NW, c->f32, c->side[c->cur], c->plan + c->par, c->filt + c->par, rp, ob, c->ctl,
+                            bpart.as<double>(), bout.as<double>(), grid, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(res, bout.p, sizeof(res), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  itpp_status st = check_error(c);
+  if (st != ITPP_OK) return st;
+  *purity = res[1];
+  *value = res[0] / res[1];
   return ITPP_OK;
 }
 

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include "itpp_device.h"
+#include "itpp_readout.h"
 
 namespace itpp {
 
@@ -577,6 +578,147 @@ __global__ void export_kernel(Side s, const Plan* plan, const Filter* filt, RepP
 }
 
 // ---------------------------------------------------------------------------
+// Squared-state estimate (Sec. II.C): <O>_{2 tau} = Tr[(O rho) rho] / Tr[rho^2].
+// With rho = 2^-n sum_P a_P P, every stored string P adds a_P^2 to the purity
+// and, for each observable string Q_j it commutes with, o_j a_P a_R s to the
+// numerator, where Q_j P = s R (s = +-1) and a_R is looked up in the stored
+// state (anticommuting strings give imaginary terms that cancel in pairs).
+
+// Normalised coefficient of key k in the stored state, if stored and kept.
+template <int NW, typename T>
+__device__ inline bool lookup_coef(const Side& s, const Plan& p, const Filter& f, const RepPos& rp,
+                                   const Key<NW>& k, double& a) {
+  const int e = class_of(k, rp.nbits, p.we);
+  for (int c = 0; c < (1 << p.wc); ++c) {
+    uint64_t lo = p.base[c][e], hi = p.base[c][e] + p.cnt[c][e];
+    const uint64_t end = hi;
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (key_less(load_key<NW>(s, mid), k))
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    if (lo < end && key_eq(load_key<NW>(s, lo), k)) {
+      const T cs = coefs<T>(s)[lo];
+      if (!survives(k, (double)cs, f, rp.pos, rp.nbits)) return false;
+      a = (double)normalised<T>(cs, f.cI);
+      return true;
+    }
+  }
+  return false;
+}
+
+template <int NW, typename T>
+__global__ __launch_bounds__(256) void squared_kernel(Side s, const Plan* plan, const Filter* filt, RepPos rp,
+                                                      SqObs ob, Ctl* ctl, double* part) {
+  __shared__ double red[4][256];
+  const Plan& p = *plan;
+  const Filter f = *filt;
+  const int tid = threadIdx.x;
+  double ns = 0.0, ne = 0.0, ps = 0.0, pe = 0.0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (int c = 0; c < (1 << p.wc); ++c)
+    for (int e = 0; e < (1 << p.we); ++e) {
+      const uint64_t base = p.base[c][e], cnt = p.cnt[c][e];
+      for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + tid; i < cnt; i += stride) {
+        const Key<NW> k = load_key<NW>(s, base + i);
+        const T cs = coefs<T>(s)[base + i];
+        if (!survives(k, (double)cs, f, rp.pos, rp.nbits)) continue;
+        const double a = (double)normalised<T>(cs, f.cI);
+        double sr, er;
+        two_sum(ps, __dmul_rn(a, a), sr, er);
+        ps = sr;
+        pe = __dadd_rn(pe, er);
+        for (int j = 0; j < ob.m; ++j) {
+          int par = 0;
+#pragma unroll
+          for (int q = 0; q < NW; ++q) par ^= __popcll(k.w[q] & ob.cmask[(size_t)j * NW + q]) & 1;
+          if (par) continue;
+          Key<NW> r = k;
+#pragma unroll
+          for (int q = 0; q < NW; ++q) r.w[q] ^= ob.qmask[(size_t)j * NW + q];
+          int e4 = ob.aq[j];
+          for (int t = ob.sup_off[j]; t < ob.sup_off[j + 1]; ++t) {
+            const int xp = get_bit(k, ob.sup_pos[2 * t]), zp = get_bit(k, ob.sup_pos[2 * t + 1]);
+            const int qx = ob.sup_q[t] & 1, qz = (ob.sup_q[t] >> 1) & 1;
+            e4 += (xp & zp) - ((xp ^ qx) & (zp ^ qz)) + 2 * (qz & xp);
+          }
+          e4 &= 3;
+          if (e4 & 1) {
+            atomicMax(&ctl->error, kErrPhase);
+            continue;
+          }
+          double ar;
+          if (!lookup_coef<NW, T>(s, p, f, rp, r, ar)) continue;
+          double term = __dmul_rn(ob.coef[j], __dmul_rn(a, ar));
+          if (e4 == 2) term = -term;
+          two_sum(ns, term, sr, er);
+          ns = sr;
+          ne = __dadd_rn(ne, er);
+        }
+      }
+    }
+  red[0][tid] = ns;
+  red[1][tid] = ne;
+  red[2][tid] = ps;
+  red[3][tid] = pe;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+      double sr, er;
+      two_sum(red[0][tid], red[0][tid + h], sr, er);
+      red[0][tid] = sr;
+      red[1][tid] = __dadd_rn(__dadd_rn(red[1][tid], red[1][tid + h]), er);
+      two_sum(red[2][tid], red[2][tid + h], sr, er);
+      red[2][tid] = sr;
+      red[3][tid] = __dadd_rn(__dadd_rn(red[3][tid], red[3][tid + h]), er);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    part[4 * blockIdx.x + 0] = red[0][0];
+    part[4 * blockIdx.x + 1] = red[1][0];
+    part[4 * blockIdx.x + 2] = red[2][0];
+    part[4 * blockIdx.x + 3] = red[3][0];
+  }
+}
+
+// The per-block partials in a fixed order (one block of 256 threads).
+__global__ __launch_bounds__(256) void squared_reduce(const double* part, int nparts, double* out) {
+  __shared__ double red[4][256];
+  const int tid = threadIdx.x;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = tid; b < nparts; b += 256) {
+    double sr, er;
+    two_sum(v[0], part[4 * b + 0], sr, er);
+    v[0] = sr;
+    v[1] = __dadd_rn(__dadd_rn(v[1], part[4 * b + 1]), er);
+    two_sum(v[2], part[4 * b + 2], sr, er);
+    v[2] = sr;
+    v[3] = __dadd_rn(__dadd_rn(v[3], part[4 * b + 3]), er);
+  }
+  for (int q = 0; q < 4; ++q) red[q][tid] = v[q];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+      double sr, er;
+      two_sum(red[0][tid], red[0][tid + h], sr, er);
+      red[0][tid] = sr;
+      red[1][tid] = __dadd_rn(__dadd_rn(red[1][tid], red[1][tid + h]), er);
+      two_sum(red[2][tid], red[2][tid + h], sr, er);
+      red[2][tid] = sr;
+      red[3][tid] = __dadd_rn(__dadd_rn(red[3][tid], red[3][tid + h]), er);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[0] = __dadd_rn(red[0][0], red[1][0]);
+    out[1] = __dadd_rn(red[2][0], red[3][0]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Reverse sweep support.
 
 // Copy a stored state into a packed layout: region (c, e) at the running sum
@@ -738,6 +880,15 @@ hipError_t launch_select(int nw, int f32, Side out, const Plan* plan_out, const 
     hipLaunchKernelGGL((select_collect<NWC, TC>), dim3(grid), dim3(256), 0, st, out, plan_out, ctl, sel);
     hipLaunchKernelGGL(select_exact<NWC>, dim3(1), dim3(1024), 0, st, out, filt_out, ctl, sel, rp);
   });
+  return hipGetLastError();
+}
+
+hipError_t launch_squared(int nw, int f32, Side s, const Plan* plan, const Filter* filt, const RepPos& rp,
+                          const SqObs& ob, Ctl* ctl, double* part, double* out, int grid, hipStream_t st) {
+  ITPP_DISPATCH(nw, f32,
+                hipLaunchKernelGGL((squared_kernel<NWC, TC>), dim3(grid), dim3(256), 0, st, s, plan, filt, rp, ob,
+                                   ctl, part));
+  hipLaunchKernelGGL(squared_reduce, dim3(1), dim3(256), 0, st, part, grid, out);
   return hipGetLastError();
 }
 
