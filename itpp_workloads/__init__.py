@@ -369,3 +369,40 @@ def synthetic_state_words(n: int, count: int, seed: int, partner: Optional[str] 
     sign = np.where(rng.random(m) < 0.5, -1.0, 1.0)
     coef = np.concatenate([[1.0], sign * np.exp2(-step * k.astype(np.float64))])
     return x, z, coef
+
+
+# ---------------------------------------------------------------------------
+# Two-dimensional transverse-field Ising model (a general lattice Hamiltonian).
+# ---------------------------------------------------------------------------
+
+def tfim_2d_terms(Lx: int, Ly: int, J: float, h: float, periodic: bool = False) -> Tuple[List[str], List[float], int]:
+    """H = -J sum_<ij> Z_i Z_j - h sum_i X_i on an Lx x Ly square lattice,
+    site (x, y) -> qubit x + Lx * y; horizontal bonds, then vertical bonds,
+    then the X terms.  Returns (strings, weights, number of ZZ terms)."""
+    n = Lx * Ly
+    bonds = []
+    for y in range(Ly):
+        for x in range(Lx):
+            if x + 1 < Lx or (periodic and Lx > 2):
+                bonds.append((x + Lx * y, (x + 1) % Lx + Lx * y))
+    for y in range(Ly):
+        for x in range(Lx):
+            if y + 1 < Ly or (periodic and Ly > 2):
+                bonds.append((x + Lx * y, x + Lx * ((y + 1) % Ly)))
+    strings = [two_site(n, min(i, j), max(i, j), "Z", "Z") for i, j in bonds]
+    alphas = [-J] * len(bonds)
+    strings += [single_site(n, i, "X") for i in range(n)]
+    alphas += [-h] * n
+    return strings, alphas, len(bonds)
+
+
+def tfim_2d_workload(name: str, Lx: int, Ly: int, J: float, h: float, periodic: bool, order: int,
+                     dtau: float, beta: float, delta: float, K: int, precision: str = "f64") -> Workload:
+    strings, alphas, n_zz = tfim_2d_terms(Lx, Ly, J, h, periodic)
+    n = Lx * Ly
+    sched = tfim_schedule(n_zz, n, order)
+    obs = {"energy_per_site": (list(strings), [a / n for a in alphas]),
+           "X0": ([single_site(n, 0, "X")], [1.0])}
+    return Workload(name=name, n=n, strings=strings, alphas=alphas, schedule=sched, dtau=dtau,
+                    n_steps=n_steps_for(beta, dtau), delta=delta, K=K, precision=precision, observables=obs,
+                    meta=dict(model="tfim_2d", Lx=Lx, Ly=Ly, J=J, h=h, periodic=periodic, order=order, beta=beta))

@@ -111,6 +111,18 @@ def test_capped_configs_bitexact(builder, steps):
     e.close()
 
 
+@pytest.mark.parametrize("Lx,Ly,periodic,K,steps", [(4, 4, True, 3000, 2), (8, 8, False, 4000, 2),
+                                                    (8, 12, True, 3000, 1)])
+def test_2d_lattices_bitexact(Lx, Ly, periodic, K, steps):
+    """Square-lattice TFIM (n = 16, 64 and 96 qubits), cap binding."""
+    w = W.tfim_2d_workload("t", Lx, Ly, 1.0, 0.7, periodic, 1, 0.05, 1.0, 1e-9, K)
+    e, st, S = gpu_state(w, steps=steps)
+    o = c_oracle.run_workload(w, n_steps=steps)
+    assert_same_state(o.state(), S)
+    assert st["cap_hit"] == 1
+    e.close()
+
+
 def test_massive_ties_h0():
     """h = 0: coefficients are exact powers tanh(beta J)^k, so the cap cuts
     through large groups of equal values; the canonical tie-break decides."""

@@ -90,6 +90,19 @@ def test_untruncated_equals_trotterized_dense(n, periodic, order):
     assert S["I" * n] == 1.0
 
 
+@pytest.mark.parametrize("Lx,Ly,periodic,order", [(2, 2, False, 1), (3, 2, False, 2), (3, 3, True, 1)])
+def test_untruncated_2d_lattice_equals_trotterized_dense(Lx, Ly, periodic, order):
+    """A two-dimensional TFIM (square lattice) is propagated like any other
+    Hamiltonian: without truncation it reproduces Eq. ThermalTrotter."""
+    w = W.tfim_2d_workload("t", Lx, Ly, 1.0, 0.7, periodic, order, 0.05, 0.4, 0.0, 1 << 40)
+    n = Lx * Ly
+    assert len(w.strings) == (Lx * Ly * 2 if periodic else (Lx - 1) * Ly + Lx * (Ly - 1)) + n
+    S, _ = itpp.run_workload(w)
+    rho = dense.trotter_thermal(w.strings, w.alphas, w.schedule, w.dtau, w.n_steps)
+    A = dense.pauli_coefficients(rho, tol=1e-14)
+    assert _coef_err(S, A) < 1e-12
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_untruncated_random_hamiltonian_with_y_terms(seed):
     w = W.random_workload("r", 4, 7, seed, 0.1, 4, 0.0, 1 << 40, max_weight=3, local=False)
