@@ -25,7 +25,9 @@ FP64 form on the same GPU (one step = one whole run of its workload):
            forward; d<H>/dJ, d<H>/dh, d<H>/dbeta;
   squared  the benchmark chain at cap 2^20 after beta = 2: <H>/n and <Z0 Z1>
            at 2 beta from the squared state (Tr[(O rho) rho] / Tr[rho^2]),
-           in stored strings x observable strings per second.
+           in stored strings x observable strings per second;
+  realtime a synthetic state of 2^24 strings on the benchmark chain, one
+           Trotter step of real-time gates (Sec. II.B rule), cap 2^24.
 """
 from __future__ import annotations
 
@@ -120,7 +122,7 @@ def parse():
     ap.add_argument("--beta", type=float, default=2.0, help="final inverse temperature (default 2)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form", choices=["fp64", "fp32", "batched", "adjoint", "squared"], default="fp64")
+    ap.add_argument("--form", choices=["fp64", "fp32", "batched", "adjoint", "squared", "realtime"], default="fp64")
     ap.add_argument("--progress", action="store_true", help="print a line after every tenth of the Trotter steps")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="end with three 256 MiB device copies (the byte counters' calibration in a --pmc run)")
@@ -384,6 +386,68 @@ def run_form_squared(args):
     return line, w
 
 
+def run_form_realtime(args):
+    """Real-time gates (Sec. II.B rule) on the benchmark chain at cap 2^24:
+    a synthetic state of 2^24 strings is loaded, one Trotter step is timed."""
+    import torch
+
+    import itpp_workloads as W
+    import paper_2601_14400_amd as P
+
+    K = args.K
+    w = W.config2(K=K)
+    # about 1e6 distinct magnitudes in [2^-19.5, 1): ties at the cap stay small
+    x, z, c = W.synthetic_state_words(w.n, K, seed=41, partner=w.strings[w.schedule[0][0]], levels=1 << 20,
+                                      step=19.5 / (1 << 20))
+    progress("synthetic state generated")
+    e = P.engine_for(w)
+    e.import_words(x, z, c)
+    e.set_option("real_time", 1)
+    e.evolve_gates(w.dtau, 20)  # warm-up; the prediction of the K-th value settles
+    e.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = e.evolve(w.dtau, 1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    roof = roofline_of(e.timing())
+    e.close()
+    progress(f"one real-time Trotter step: {dt:.3f} s")
+    line = base_line(args, st["term_updates"] / dt, dt * 1e3, "f64",
+                     {"workload": f"tfim_n64_open_strang_dtau0.02_K{K}_realtime_synthetic_state", "form": "realtime",
+                      "n_qubits": w.n, "K": K, "gates": st["n_gates"], "cap_hit": st["cap_hit"]})
+    line["roofline"] = roof
+    line["form"] = {"term_updates": st["term_updates"], "final_terms": st["n_terms"], "seconds": dt}
+    return line, w
+
+
+def cpu_baseline_realtime(w, budget_s: float):
+    """The real-time oracle (pure Python), gate by gate on a synthetic state of
+    2^15 strings of the same chain, until the time budget is used."""
+    import math as _m
+
+    import itpp_workloads as W
+    from oracle import realtime as RT
+
+    x, z, c = W.synthetic_state_words(w.n, 1 << 15, seed=41, partner=w.strings[w.schedule[0][0]])
+    from paper_2601_14400_amd import words_to_strings  # marshalling only
+
+    S = dict(zip(words_to_strings(x, z, w.n), c.tolist()))
+    t0 = time.perf_counter()
+    gates, updates = 0, 0.0
+    while time.perf_counter() - t0 < budget_s:
+        k, mlt = w.schedule[gates % len(w.schedule)]
+        th = w.alphas[k] * mlt * w.dtau
+        updates += len(S)
+        S = RT.truncate(RT.apply_gate_real(S, w.strings[k], _m.cos(th), _m.sin(th)), w.delta, w.K)
+        gates += 1
+    dt = time.perf_counter() - t0
+    return {"value": updates / dt, "unit": "term-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"Python dict real-time oracle, {gates} gates of the same chain on a synthetic state of "
+                      f"{1 << 15} strings ({updates:.3e} term updates in {dt:.1f} s); "
+                      f"host {platform.processor() or platform.machine()}, os.cpu_count()={os.cpu_count()}"}
+
+
 def cpu_baseline_squared(w, budget_s: float):
     """The oracle's squared-state energy on the C++ oracle's own state after
     the first gates of the same workload, grown until the evaluation covers
@@ -426,10 +490,10 @@ def main():
     if args.form != "fp64":
         torch.cuda.set_device(0)
         line, w = {"fp32": run_form_fp32, "batched": run_form_batched, "adjoint": run_form_adjoint,
-                   "squared": run_form_squared}[args.form](args)
+                   "squared": run_form_squared, "realtime": run_form_realtime}[args.form](args)
         if not args.no_cpu_baseline:
             progress("cpu baseline")
-            base = cpu_baseline_squared if args.form == "squared" else cpu_baseline
+            base = {"squared": cpu_baseline_squared, "realtime": cpu_baseline_realtime}.get(args.form, cpu_baseline)
             line["cpu_baseline"] = base(w, args.cpu_seconds)
         print(json.dumps(line), flush=True)
         return

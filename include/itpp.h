@@ -253,8 +253,22 @@ itpp_status itpp_backward(itpp_ctx ctx, int32_t n_strings, const uint64_t* x, co
  *  ITPP_OPT_GATE_SHAPE (default 0 for n <= 64, 1 above): 0 = one 1024-thread workgroup per CU
  *    with 4000 (n <= 64) or 2000 (n <= 128) strings per tile; 1 = two
  *    512-thread workgroups per CU with 2000 or 1500 strings per tile (more
- *    tiles in flight, better for small states). */
-typedef enum { ITPP_OPT_SPECULATION = 1, ITPP_OPT_SPEC_MARGIN = 2, ITPP_OPT_GATE_SHAPE = 3 } itpp_option;
+ *    tiles in flight, better for small states).
+ * One option changes the method instead:
+ *  ITPP_OPT_REAL_TIME (default 0): 1 applies the real-time rule of Sec. II.B
+ *    to the following gates, U_Q(theta)^dagger P U_Q(theta) with
+ *    U_Q = exp(-i theta Q / 2) and theta = alpha_k * mult * dtau: commuting
+ *    strings pass unchanged, anticommuting ones become
+ *    cos(theta) P + i sin(theta) Q P (real: i Q P = -+R).  Truncation is
+ *    unchanged; the identity coefficient stays 1.  Start from a state given
+ *    by itpp_import (rho = I does not move).  Disables the reverse sweep of
+ *    the run. */
+typedef enum {
+  ITPP_OPT_SPECULATION = 1,
+  ITPP_OPT_SPEC_MARGIN = 2,
+  ITPP_OPT_GATE_SHAPE = 3,
+  ITPP_OPT_REAL_TIME = 4
+} itpp_option;
 itpp_status itpp_set_option(itpp_ctx ctx, int32_t option, double value);
 
 /* Enable (1) or disable (0) per-gate HIP event timing; enabling clears the

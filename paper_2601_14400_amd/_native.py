@@ -296,7 +296,7 @@ class Engine:
                 "spec_gates": st.spec_gates, "spec_retries": st.spec_retries}
 
     def set_option(self, name: str, value: float):
-        opt = {"speculation": 1, "spec_margin": 2, "gate_shape": 3}[name]
+        opt = {"speculation": 1, "spec_margin": 2, "gate_shape": 3, "real_time": 4}[name]
         self._check(self._lib.itpp_set_option(self._h, opt, float(value)))
 
     def set_timing(self, enable: bool = True):

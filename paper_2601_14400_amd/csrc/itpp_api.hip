@@ -93,6 +93,7 @@ struct itpp_ctx_s {
   uint32_t epoch = 1;
   uint64_t serial = 1;
   bool speculate = true;
+  bool real_time = false;       // gates follow the real-time rule (ITPP_OPT_REAL_TIME)
   double spec_mult = 0.98;
   int64_t retries_total = 0;
   std::string err;
@@ -734,8 +735,8 @@ static itpp_status build_gate(itpp_ctx c, int i, const std::vector<int>& pos, do
   const TermInfo& t2 = c->terms[c->sched_term[c->glist[(i + 2) % G]]];
   const double theta = t.alpha * c->sched_mult[sg] * dtau;
   std::memset(&gp, 0, sizeof(gp));
-  gp.ch = std::cosh(theta);
-  gp.sh = std::sinh(theta);
+  gp.ch = c->real_time ? std::cos(theta) : std::cosh(theta);
+  gp.sh = c->real_time ? std::sin(theta) : std::sinh(theta);
   gp.nbits = nbits;
   gp.w = (int)t.F.size();
   gp.w1 = (int)t1.F.size();
@@ -810,7 +811,8 @@ static itpp_status enqueue_gate(itpp_ctx c, double dtau, bool spec) {
     HIP_TRY(c, next_event(c, &e2));
     HIP_TRY(c, hipEventRecord(e0, c->stream));
   }
-  HIP_TRY(c, launch_gate(c->NW, c->f32, c->shape, gp, c->side[in], c->side[out], c->plan + pin, c->plan + pout,
+  HIP_TRY(c, (c->real_time ? launch_gate_rt : launch_gate)(c->NW, c->f32, c->shape, gp, c->side[in], c->side[out],
+                                                           c->plan + pin, c->plan + pout,
                          c->filt + pin, c->ctl, c->status, c->part, c->cus * gate_wgs_per_cu(c->shape), c->stream));
   if (c->timing) HIP_TRY(c, hipEventRecord(e1, c->stream));
   HIP_TRY(c, launch_select(c->NW, c->f32, c->side[out], c->plan + pout, c->filt + pin, c->filt + pout, c->plan + pin,
@@ -851,6 +853,10 @@ static itpp_status run_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stat
   int64_t done = 0;
   bool nospec_next = false;
   std::vector<HostSnap> snaps;
+  if (n_gates > 0 && G > 0 && c->real_time) {
+    c->fwd_valid = false;  // the reverse sweep replays imaginary-time gates only
+    free_ckpts(c);
+  }
   if (n_gates > 0 && G > 0) {
     if (c->fwd_gates == 0) {
       c->fwd_dtau = dtau;
@@ -957,6 +963,15 @@ itpp_status itpp_set_option(itpp_ctx c, int32_t option, double value) {
     case ITPP_OPT_GATE_SHAPE:
       if (value != 0.0 && value != 1.0) return fail(c, ITPP_ERR_ARG, "gate shape must be 0 or 1");
       c->shape = (int)value;
+      return ITPP_OK;
+    case ITPP_OPT_REAL_TIME:
+      if (value != 0.0 && value != 1.0) return fail(c, ITPP_ERR_ARG, "real time must be 0 or 1");
+      c->real_time = value != 0.0;
+      // the reverse sweep replays imaginary-time gates only
+      if (c->real_time) {
+        c->fwd_valid = false;
+        free_ckpts(c);
+      }
       return ITPP_OK;
     default:
       return fail(c, ITPP_ERR_ARG, "unknown option");

@@ -317,7 +317,12 @@ __device__ void adjoint_tile(Smem& sm, const AdjArgs& adj, const GateParams& gp,
 // (adjoint of Eq. ITPP_PropRules, of the kept-set restriction and of the
 // division by the identity coefficient), with per-tile partial sums of
 // dL/dtheta and of sum lambda a.
-template <int NW, int BLOCK, int TILE, typename T, bool ADJ>
+//
+// RT = true applies the real-time rule of Sec. II.B instead (gp.ch = cos,
+// gp.sh = sin): anticommuting strings branch, cos(theta) P + i sin(theta) Q P,
+// with Q P = i^k R for odd k; commuting ones pass unchanged.  Info bit 1 then
+// marks the branching (anticommuting) strings and the merge-join is the same.
+template <int NW, int BLOCK, int TILE, typename T, bool ADJ, bool RT = false>
 __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, Side out,
                                                       const Plan* __restrict__ plan_in,
                                                       Plan* __restrict__ plan_out,
@@ -434,7 +439,8 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
       Key<NW> k = load_key<NW>(in, p);
       const T cs = coefs<T>(in)[p];
       const bool sv = survives(k, (double)cs, fin, gp.pos_in, nbits);
-      const bool comm = !anticommutes(k, gp);
+      bool comm = !anticommutes(k, gp);
+      if constexpr (RT) comm = !comm;  // the strings that branch
       if (!isA) k = xor_top(k, nbits, w);  // B' = B xor Q lives in class cA's key space
 #pragma unroll
       for (int q = 0; q < NW; ++q) sm.key[q][x] = k.w[q];
@@ -493,8 +499,16 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
             bool neg = false;
             if (comm) {
               const int e4 = phase_negative(ownk, gp);
-              if (e4 & 1) atomicMax(&ctl->error, kErrPhase);
-              neg = (e4 == 2);
+              if constexpr (RT) {
+                // i Q P = i^(k+1) R: the own branch is -sin c for k = 1 and
+                // +sin c for k = 3; the partner's branch (its phase is i^-k)
+                // arrives with the opposite sign
+                if (!(e4 & 1)) atomicMax(&ctl->error, kErrPhase);
+                neg = (e4 == 3) != paired;
+              } else {
+                if (e4 & 1) atomicMax(&ctl->error, kErrPhase);
+                neg = (e4 == 2);
+              }
               if (neg) inf |= 512u;
             }
             T vs, vb;
@@ -889,15 +903,15 @@ hipError_t launch_partition(int nw, const GateParams& gp, Side in, const Plan* p
   return hipGetLastError();
 }
 
-template <int SHAPE>
+template <int SHAPE, bool RT>
 void launch_gate_shape(int nw, int f32, const GateParams& gp, Side in, Side out, const Plan* plan_in,
                        Plan* plan_out, const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part,
                        int grid, hipStream_t st) {
   using S = GateShape<SHAPE>;
   const AdjArgs none{};
   ITPP_DISPATCH(nw, f32,
-                hipLaunchKernelGGL((gate_kernel<NWC, S::block, S::template tile<NWC>(), TC, false>), dim3(grid),
-                                   dim3(S::block), 0, st, gp, in, out, plan_in, plan_out, filt_in,
+                hipLaunchKernelGGL((gate_kernel<NWC, S::block, S::template tile<NWC>(), TC, false, RT>),
+                                   dim3(grid), dim3(S::block), 0, st, gp, in, out, plan_in, plan_out, filt_in,
                                    (const uint64_t*)part, ctl, status, none));
 }
 
@@ -905,9 +919,19 @@ hipError_t launch_gate(int nw, int f32, int shape, const GateParams& gp, Side in
                        Plan* plan_out, const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part,
                        int grid, hipStream_t st) {
   if (shape == 1)
-    launch_gate_shape<1>(nw, f32, gp, in, out, plan_in, plan_out, filt_in, ctl, status, part, grid, st);
+    launch_gate_shape<1, false>(nw, f32, gp, in, out, plan_in, plan_out, filt_in, ctl, status, part, grid, st);
   else
-    launch_gate_shape<0>(nw, f32, gp, in, out, plan_in, plan_out, filt_in, ctl, status, part, grid, st);
+    launch_gate_shape<0, false>(nw, f32, gp, in, out, plan_in, plan_out, filt_in, ctl, status, part, grid, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_gate_rt(int nw, int f32, int shape, const GateParams& gp, Side in, Side out,
+                          const Plan* plan_in, Plan* plan_out, const Filter* filt_in, Ctl* ctl, TileStatus* status,
+                          uint64_t* part, int grid, hipStream_t st) {
+  if (shape == 1)
+    launch_gate_shape<1, true>(nw, f32, gp, in, out, plan_in, plan_out, filt_in, ctl, status, part, grid, st);
+  else
+    launch_gate_shape<0, true>(nw, f32, gp, in, out, plan_in, plan_out, filt_in, ctl, status, part, grid, st);
   return hipGetLastError();
 }
 

@@ -177,6 +177,10 @@ hipError_t launch_partition(int nw, const GateParams& gp, Side in, const Plan* p
 hipError_t launch_gate(int nw, int f32, int shape, const GateParams& gp, Side in, Side out, const Plan* plan_in,
                        Plan* plan_out, const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part,
                        int grid, hipStream_t st);
+// The same gate under the real-time rule (gp.ch = cos, gp.sh = sin).
+hipError_t launch_gate_rt(int nw, int f32, int shape, const GateParams& gp, Side in, Side out, const Plan* plan_in,
+                       Plan* plan_out, const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part,
+                       int grid, hipStream_t st);
 hipError_t launch_select(int nw, int f32, Side out, const Plan* plan_out, const Filter* filt_in,
                          Filter* filt_out, Plan* plan_next, Ctl* ctl, SelBuf sel, const RepPos& rp,
                          int64_t K, int cap_fail, int spec, uint64_t serial, int grid, hipStream_t st);
