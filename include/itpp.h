@@ -12,6 +12,8 @@
  * max_terms strings keep the identity and the max_terms-1 largest |c|, ties
  * broken by the smaller canonical key) and divided by the identity
  * coefficient (Algorithm 1; per-gate normalisation as Sec. II.C requires).
+ * ITPP_OPT_REAL_TIME switches the gates to the real-time rule of Sec. II.B;
+ * itpp_import loads another starting state.
  *
  * Conventions shared by every entry point
  * --------------------------------------
@@ -25,11 +27,13 @@
  *    the x bits as one n-bit integer, then the z bits as one n-bit integer.
  *  - Gate angle: theta = alpha[term] * mult[gate] * dtau, evaluated left to
  *    right in IEEE double; cosh and sinh are taken once per gate on the host.
- *  - All pointers are host pointers; the caller owns them, the library copies
- *    what it needs during the call and keeps no reference.  Device state is
- *    owned by the context.
+ *  - All pointers are host pointers, except the arrays of the two *_device
+ *    entry points; the caller owns them, the library copies what it needs
+ *    during the call and keeps no reference.  Device state is owned by the
+ *    context.
  *  - Every call returns an itpp_status; ITPP_OK is 0.  On error nothing is
- *    written to output arguments and itpp_last_error() describes the cause.
+ *    written to output arguments (except the required capacity that the
+ *    export calls report) and itpp_last_error() describes the cause.
  *  - A context is used from one host thread at a time.
  */
 #ifndef ITPP_H_
