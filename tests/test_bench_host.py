@@ -66,3 +66,13 @@ def test_committed_record_matches_the_kernel_source():
     """The committed traffic figure was taken on the kernel as it stands."""
     rec = json.load(open(os.path.join(ROOT, "profiles", "gate_kernel_traffic_tfim_n64_open_K2e24.json")))
     assert rec["kernel_source_sha256"] == bench.kernel_source_hash()
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    import subprocess
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
