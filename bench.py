@@ -525,7 +525,7 @@ def main():
             st = tot
         else:
             st = eng.evolve(w.dtau, w.n_steps)
-        vals = {k: eng.expect(s, c) for k, (s, c) in obs.items() if k in ("energy_per_site", "Z0Z1", "Z0Z8")}
+        vals = {k: eng.expect(s, c) for k, (s, c) in obs.items() if k == "energy_per_site" or k.startswith("Z0Z")}
         return st, vals
 
     for _ in range(args.warmup):
