@@ -232,16 +232,16 @@ itpp_status itpp_export_device(itpp_ctx ctx, int64_t capacity, uint64_t* x, uint
  * workspace_bytes bounds the device memory of one itpp_backward call for its
  * recomputed states (0: 70% of the free device memory).  ITPP_F64 contexts
  * only (ITPP_ERR_ARG otherwise).  Takes effect for the gates applied after
- * the next reset or set_schedule. */
+ * the next reset, set_schedule or itpp_import. */
 itpp_status itpp_set_adjoint(itpp_ctx ctx, int32_t every_steps, int64_t workspace_bytes);
 
 /* For L = sum_j coef[j] a_{P_j} of the current state (strings as in
  * itpp_expect): *value = L, d_alpha[k] = dL/dalpha_k for every Hamiltonian
  * term (n_terms doubles, zero for identity terms and unscheduled terms),
  * *d_dtau = dL/ddtau, and, if d_theta is not NULL, dL/dtheta for every
- * elementary gate applied since the last reset (in order).  Requires a
- * forward run since the last reset with itpp_set_adjoint enabled and one
- * dtau (ITPP_ERR_STATE otherwise).  Between the stored copies the states are
+ * elementary gate applied since the last reset or itpp_import (in order).
+ * Requires a forward run since then with itpp_set_adjoint enabled, one dtau
+ * and imaginary-time gates only (ITPP_ERR_STATE otherwise).  Between the stored copies the states are
  * recomputed (sub-checkpoints every ~sqrt(segment) gates); ITPP_ERR_OOM if
  * the workspace cannot hold them.  The current state is the same after the
  * call; after an error it needs a reset. */
