@@ -48,11 +48,13 @@ class GateRecord:
 
 def forward_record(n: int, strings: Sequence[str], alphas: Sequence[float],
                    schedule: Sequence[Tuple[int, float]], dtau: float, n_steps: int,
-                   delta: float, K: int) -> Tuple[Dict[str, float], List[GateRecord]]:
+                   delta: float, K: int,
+                   S0: Optional[Dict[str, float]] = None) -> Tuple[Dict[str, float], List[GateRecord]]:
     """Algorithm 1 exactly as ``itpp.evolve``, keeping what the reverse sweep
-    needs for every gate."""
+    needs for every gate; from ``S0`` (normalised, a_I = 1) instead of
+    rho = I when given."""
     ident = itpp.identity(n)
-    S = {ident: 1.0}
+    S = {ident: 1.0} if S0 is None else dict(S0)
     recs: List[GateRecord] = []
     for _ in range(n_steps):
         for k, m in schedule:
@@ -131,10 +133,11 @@ def parameter_gradients(strings: Sequence[str], alphas: Sequence[float], recs: S
 
 
 def gradients(w, obs_strings: Sequence[str], obs_coefs: Sequence[float],
-              n_steps: Optional[int] = None):
-    """``(L, dL/dalpha, dL/ddtau, dL/dtheta per gate)`` for a workload."""
+              n_steps: Optional[int] = None, S0: Optional[Dict[str, float]] = None):
+    """``(L, dL/dalpha, dL/ddtau, dL/dtheta per gate)`` for a workload, from
+    ``S0`` when given (the parameters do not act on it)."""
     steps = w.n_steps if n_steps is None else n_steps
-    a, recs = forward_record(w.n, w.strings, w.alphas, w.schedule, w.dtau, steps, w.delta, w.K)
+    a, recs = forward_record(w.n, w.strings, w.alphas, w.schedule, w.dtau, steps, w.delta, w.K, S0)
     L, dth, _ = backward(w.n, w.strings, recs, a, obs_strings, obs_coefs)
     da, dd = parameter_gradients(w.strings, w.alphas, recs, dth, w.dtau)
     return L, da, dd, dth

@@ -175,3 +175,34 @@ def test_autograd_tfim_parameters():
     assert abs(float(gh) - rh) < 1e-10 * max(1.0, abs(rh))
     assert abs(float(gb) - rb) < 1e-10 * max(1.0, abs(rb))
     eng.close()
+
+
+def test_reverse_sweep_from_a_loaded_state():
+    """The first forward checkpoint is whatever state the run starts from: a
+    state loaded with itpp_import gives the oracle's derivatives from that
+    state."""
+    w = W.tfim_workload("t", 12, 1.0, 0.9, True, 1, 0.05, 1.0, 1e-9, 2000)
+    x, z, c = W.synthetic_state_words(w.n, 600, seed=51, partner=w.strings[w.schedule[0][0]])
+    S0 = {}
+    for i in range(len(c)):
+        s = []
+        for j in range(w.n):
+            xb = (int(x[i][j >> 6]) >> (j & 63)) & 1
+            zb = (int(z[i][j >> 6]) >> (j & 63)) & 1
+            s.append("IXZY"[xb | (zb << 1)])
+        S0["".join(s)] = float(c[i])
+    obs = (w.strings, [a / w.n for a in w.alphas])
+    e = P.engine_for(w)
+    e.load(S0)
+    e.set_adjoint(1)
+    st = e.evolve(w.dtau, 2)
+    L, da, dd, dth = e.backward(*obs, want_theta=True)
+    Lr, dar, ddr, dthr = AD.gradients(w, *obs, n_steps=2, S0=S0)
+    assert st["cap_hit"] == 1
+    assert len(dth) == len(dthr)
+    scale = max(1e-300, max(abs(v) for v in dthr))
+    assert max(abs(a - b) for a, b in zip(dth, dthr)) <= TOL * scale
+    assert abs(L - Lr) <= 1e-13 * max(1.0, abs(Lr))
+    assert max(abs(a - b) for a, b in zip(da, dar)) <= TOL * max(1.0, max(abs(v) for v in dar))
+    assert abs(dd - ddr) <= TOL * max(1.0, abs(ddr))
+    e.close()
