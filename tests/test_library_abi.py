@@ -58,3 +58,11 @@ def test_string_packing_roundtrip():
     assert x.shape == (3, 2)
     assert words_to_strings(x, z, 80) == strs
     assert int(x[0, 0]) & 0b0110 == 0b0110 and int(z[0, 0]) & 0b1100 == 0b1100
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """No fallback: a missing shared library is an import error."""
+    from paper_2601_14400_amd import _native
+
+    with pytest.raises(ImportError):
+        _native.load_library(str(tmp_path / "libitpp.so"))
