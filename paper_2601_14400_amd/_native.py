@@ -396,11 +396,11 @@ class Batch:
     (see itpp_batch_* in include/itpp.h).  ``instances[i]`` is an Engine
     view of instance i for the single-instance calls."""
 
-    def __init__(self, configs: Sequence[Dict]):
+    def __init__(self, instance_configs: Sequence[Dict]):
         self._lib = load_library()
-        n = len(configs)
+        n = len(instance_configs)
         arr = (ItppConfig * n)()
-        for i, c in enumerate(configs):
+        for i, c in enumerate(instance_configs):
             arr[i].n_qubits = int(c["n_qubits"])
             arr[i].precision = {"f64": 0, "f32": 1}[c.get("precision", "f64")]
             arr[i].threshold = float(c["threshold"])
@@ -415,7 +415,7 @@ class Batch:
             raise ItppError(rc, "itpp_batch_create: " + (msg.decode() if msg else ""))
         self._h = h
         self.instances = [Engine._borrowed(self._lib, ctypes.c_void_p(self._lib.itpp_batch_instance(h, i)),
-                                           configs[i]["n_qubits"]) for i in range(n)]
+                                           instance_configs[i]["n_qubits"]) for i in range(n)]
 
     def _check(self, rc: int):
         if rc != 0:
