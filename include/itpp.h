@@ -239,14 +239,21 @@ itpp_status itpp_set_adjoint(itpp_ctx ctx, int32_t every_steps, int64_t workspac
  * itpp_expect): *value = L, d_alpha[k] = dL/dalpha_k for every Hamiltonian
  * term (n_terms doubles, zero for identity terms and unscheduled terms),
  * *d_dtau = dL/ddtau, and, if d_theta is not NULL, dL/dtheta for every
- * elementary gate applied since the last reset or itpp_import (in order).
+ * elementary gate applied since the last reset or itpp_import (in order):
+ * d_theta_capacity doubles are available there, and ITPP_ERR_ARG is returned
+ * (nothing written) when that is fewer than the gates (itpp_num_gates).
  * Requires a forward run since then with itpp_set_adjoint enabled, one dtau
  * and imaginary-time gates only (ITPP_ERR_STATE otherwise).  Between the stored copies the states are
  * recomputed (sub-checkpoints every ~sqrt(segment) gates); ITPP_ERR_OOM if
  * the workspace cannot hold them.  The current state is the same after the
  * call; after an error it needs a reset. */
 itpp_status itpp_backward(itpp_ctx ctx, int32_t n_strings, const uint64_t* x, const uint64_t* z,
-                          const double* coef, double* value, double* d_alpha, double* d_dtau, double* d_theta);
+                          const double* coef, double* value, double* d_alpha, double* d_dtau, double* d_theta,
+                          int64_t d_theta_capacity);
+
+/* Elementary gates applied since the last reset, itpp_set_schedule or
+ * itpp_import (the length of itpp_backward's d_theta). */
+itpp_status itpp_num_gates(itpp_ctx ctx, int64_t* out);
 
 /* Engine options (results do not depend on them; only speed does).
  *  ITPP_OPT_SPECULATION (default 1): once the cap binds, a gate writes only

@@ -5,7 +5,7 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
-from typing import Dict, Sequence, Tuple
+from typing import Dict, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -50,6 +50,18 @@ def _load():
         lib.itpp_oracle_export.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         lib.itpp_oracle_import.argtypes = [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_char_p,
                                            ctypes.c_void_p]
+        lib.itpp_oracle_gradients.restype = ctypes.c_int
+        lib.itpp_oracle_gradients.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_char_p,
+                                              ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_double, ctypes.c_longlong,
+                                              ctypes.c_double, ctypes.c_longlong, ctypes.c_int,
+                                              ctypes.c_char_p, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p,
+                                              ctypes.c_void_p]
+        lib.itpp_oracle_import_words.argtypes = [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_int,
+                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        lib.itpp_oracle_export_words.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                                 ctypes.c_void_p, ctypes.c_void_p]
         _lib = lib
     return _lib
 
@@ -103,6 +115,51 @@ class COracle:
         buf = "".join(keys).encode("ascii")
         coef = np.ascontiguousarray([S[k] for k in keys], dtype=np.float64)
         self._lib.itpp_oracle_import(self._h, len(keys), buf, coef.ctypes.data)
+
+
+    def load_words(self, x: np.ndarray, z: np.ndarray, coef: np.ndarray) -> None:
+        """Replace the state by strings given as canonical words, shape (m, W)."""
+        x = np.ascontiguousarray(x, dtype=np.uint64)
+        z = np.ascontiguousarray(z, dtype=np.uint64)
+        c = np.ascontiguousarray(coef, dtype=np.float64)
+        self._lib.itpp_oracle_import_words(self._h, len(c), x.shape[1], x.ctypes.data, z.ctypes.data,
+                                           c.ctypes.data)
+
+    def export_words(self, W: int) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+        """The state as canonical words in ascending (X, Z) order."""
+        m = self.size()
+        x = np.zeros((m, W), dtype=np.uint64)
+        z = np.zeros((m, W), dtype=np.uint64)
+        c = np.zeros(m, dtype=np.float64)
+        self._lib.itpp_oracle_export_words(self._h, W, x.ctypes.data, z.ctypes.data, c.ctypes.data)
+        return x, z, c
+
+    def gradients(self, w, obs_strings: Sequence[str], obs_coefs: Sequence[float],
+                  n_steps: Optional[int] = None):
+        """Reverse-mode derivatives from the current state (the steps of
+        ``oracle.adjoint``): ``(L, dL/dalpha, dL/ddtau, dL/dtheta per gate)``.
+        The state becomes the forward run's final state."""
+        steps = w.n_steps if n_steps is None else n_steps
+        ident = "I" * w.n
+        G = steps * sum(1 for k, _ in w.schedule if w.strings[k] != ident)
+        buf = "".join(w.strings).encode("ascii")
+        a = np.ascontiguousarray(w.alphas, dtype=np.float64)
+        ti = np.ascontiguousarray([k for k, _ in w.schedule], dtype=np.int32)
+        mu = np.ascontiguousarray([m for _, m in w.schedule], dtype=np.float64)
+        ob = "".join(obs_strings).encode("ascii")
+        oc = np.ascontiguousarray(obs_coefs, dtype=np.float64)
+        L = ctypes.c_double(0.0)
+        dd = ctypes.c_double(0.0)
+        dth = np.zeros(max(G, 1), dtype=np.float64)
+        da = np.zeros(len(w.strings), dtype=np.float64)
+        rc = self._lib.itpp_oracle_gradients(self._h, len(w.strings), buf, a.ctypes.data, len(w.schedule),
+                                             ti.ctypes.data, mu.ctypes.data, float(w.dtau), int(steps),
+                                             float(w.delta), int(w.K), len(oc), ob, oc.ctypes.data,
+                                             ctypes.byref(L), dth.ctypes.data, G, da.ctypes.data,
+                                             ctypes.byref(dd))
+        if rc != 0:
+            raise RuntimeError(self._lib.itpp_oracle_error(self._h).decode())
+        return L.value, da, dd.value, dth[:G]
 
 
 def run_workload(w, n_steps=None, K=None, precision=None) -> COracle:

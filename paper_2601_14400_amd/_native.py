@@ -23,7 +23,7 @@ STATUS = {0: "ITPP_OK", 1: "ITPP_ERR_ARG", 2: "ITPP_ERR_OOM", 3: "ITPP_ERR_CAP",
 EXPORTED = ["itpp_create", "itpp_destroy", "itpp_set_hamiltonian", "itpp_set_schedule",
             "itpp_reset", "itpp_import", "itpp_evolve", "itpp_evolve_gates", "itpp_expect", "itpp_num_terms", "itpp_export",
             "itpp_expect_device", "itpp_export_device", "itpp_expect_squared",
-            "itpp_set_adjoint", "itpp_backward", "itpp_set_option", "itpp_set_timing", "itpp_get_timing",
+            "itpp_set_adjoint", "itpp_backward", "itpp_num_gates", "itpp_set_option", "itpp_set_timing", "itpp_get_timing",
             "itpp_batch_create", "itpp_batch_destroy", "itpp_batch_instance", "itpp_batch_set_workers",
             "itpp_batch_evolve", "itpp_batch_autotune", "itpp_batch_last_error",
             "itpp_last_error", "itpp_version"]
@@ -90,7 +90,8 @@ def load_library(path: Optional[str] = None):
     lib.itpp_expect_squared.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     lib.itpp_export_device.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(i64)]
     lib.itpp_set_adjoint.argtypes = [vp, i32, i64]
-    lib.itpp_backward.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(dbl), vp, ctypes.POINTER(dbl), vp]
+    lib.itpp_backward.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(dbl), vp, ctypes.POINTER(dbl), vp, i64]
+    lib.itpp_num_gates.argtypes = [vp, ctypes.POINTER(i64)]
     lib.itpp_set_option.argtypes = [vp, i32, dbl]
     lib.itpp_set_timing.argtypes = [vp, i32]
     lib.itpp_get_timing.argtypes = [vp, ctypes.POINTER(ItppTiming)]
@@ -175,7 +176,6 @@ class Engine:
         self.n = int(n_qubits)
         self.W = (self.n + 63) // 64
         self.n_terms = 0
-        self.gates_since_reset = 0
         cfg = ItppConfig()
         cfg.n_qubits = self.n
         cfg.precision = {"f64": 0, "f32": 1}[precision]
@@ -204,7 +204,6 @@ class Engine:
         e.n = int(n_qubits)
         e.W = (e.n + 63) // 64
         e.n_terms = 0
-        e.gates_since_reset = 0
         e._h = handle
         e._owned = False
         return e
@@ -223,7 +222,6 @@ class Engine:
 
     def set_hamiltonian(self, strings: Sequence[str], alphas: Sequence[float]):
         self.n_terms = len(strings)
-        self.gates_since_reset = 0
         x, z = strings_to_words(strings, self.n)
         a = np.ascontiguousarray(alphas, dtype=np.float64)
         self._check(self._lib.itpp_set_hamiltonian(self._h, len(strings), x.ctypes.data,
@@ -233,11 +231,9 @@ class Engine:
         ti = np.ascontiguousarray([k for k, _ in schedule], dtype=np.int32)
         mu = np.ascontiguousarray([m for _, m in schedule], dtype=np.float64)
         self._check(self._lib.itpp_set_schedule(self._h, len(schedule), ti.ctypes.data, mu.ctypes.data))
-        self.gates_since_reset = 0
 
     def reset(self):
         self._check(self._lib.itpp_reset(self._h))
-        self.gates_since_reset = 0
 
     def import_words(self, x: np.ndarray, z: np.ndarray, coef: np.ndarray):
         """Replace the state by sum_j coef[j] P_j (canonical x/z words, the
@@ -259,13 +255,11 @@ class Engine:
     def evolve(self, dtau: float, n_steps: int) -> Dict[str, float]:
         st = ItppStats()
         self._check(self._lib.itpp_evolve(self._h, float(dtau), int(n_steps), ctypes.byref(st)))
-        self.gates_since_reset += st.n_gates
         return self._stats(st)
 
     def evolve_gates(self, dtau: float, n_gates: int) -> Dict[str, float]:
         st = ItppStats()
         self._check(self._lib.itpp_evolve_gates(self._h, float(dtau), int(n_gates), ctypes.byref(st)))
-        self.gates_since_reset += st.n_gates
         return self._stats(st)
 
     def set_adjoint(self, every_steps: int, workspace_bytes: int = 0):
@@ -282,12 +276,20 @@ class Engine:
         val = ctypes.c_double()
         dd = ctypes.c_double()
         da = np.zeros(max(self.n_terms, 1), dtype=np.float64)
-        dth = np.zeros(max(self.gates_since_reset, 1), dtype=np.float64) if want_theta else None
+        ng = self.num_gates()
+        dth = np.zeros(max(ng, 1), dtype=np.float64) if want_theta else None
         self._check(self._lib.itpp_backward(self._h, len(strings), x.ctypes.data, z.ctypes.data, c.ctypes.data,
                                             ctypes.byref(val), da.ctypes.data, ctypes.byref(dd),
-                                            dth.ctypes.data if dth is not None else None))
+                                            dth.ctypes.data if dth is not None else None,
+                                            len(dth) if dth is not None else 0))
         return (float(val.value), da[: self.n_terms], float(dd.value),
-                dth[: self.gates_since_reset] if dth is not None else None)
+                dth[:ng] if dth is not None else None)
+
+    def num_gates(self) -> int:
+        """Elementary gates applied since the last reset or load."""
+        v = ctypes.c_int64(0)
+        self._check(self._lib.itpp_num_gates(self._h, ctypes.byref(v)))
+        return int(v.value)
 
     @staticmethod
     def _stats(st):
@@ -433,7 +435,6 @@ class Batch:
         self._check(self._lib.itpp_batch_evolve(self._h, d.ctypes.data, k.ctypes.data, st))
         out = []
         for i in range(n):
-            self.instances[i].gates_since_reset += st[i].n_gates
             out.append(Engine._stats(st[i]))
         return out
 
@@ -442,8 +443,6 @@ class Batch:
         sh, wk, rate = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         self._check(self._lib.itpp_batch_autotune(self._h, d.ctypes.data, int(warm_gates), int(probe_gates),
                                                   ctypes.byref(sh), ctypes.byref(wk), ctypes.byref(rate)))
-        for e in self.instances:
-            e.gates_since_reset = 0
         return int(sh.value), int(wk.value), float(rate.value)
 
     def close(self):

@@ -1424,10 +1424,18 @@ itpp_status itpp_set_adjoint(itpp_ctx c, int32_t every_steps, int64_t workspace_
   return ITPP_OK;
 }
 
+itpp_status itpp_num_gates(itpp_ctx c, int64_t* out) {
+  if (!c || !out) return ITPP_ERR_ARG;
+  *out = c->fwd_gates;
+  return ITPP_OK;
+}
+
 itpp_status itpp_backward(itpp_ctx c, int32_t m, const uint64_t* x, const uint64_t* z, const double* coef,
-                          double* value, double* d_alpha, double* d_dtau, double* d_theta) {
+                          double* value, double* d_alpha, double* d_dtau, double* d_theta, int64_t d_theta_capacity) {
   if (!c) return ITPP_ERR_ARG;
   if (!value || !d_alpha || !d_dtau) return fail(c, ITPP_ERR_ARG, "null output");
+  if (d_theta && d_theta_capacity < c->fwd_gates)
+    return fail(c, ITPP_ERR_ARG, "d_theta capacity is smaller than the number of gates (itpp_num_gates)");
   if (m < 0 || (m > 0 && (!x || !z || !coef))) return fail(c, ITPP_ERR_ARG, "bad observable arrays");
   if (!c->ready) return fail(c, ITPP_ERR_STATE, "no valid state (reset required)");
   if (c->f32) return fail(c, ITPP_ERR_ARG, "the reverse sweep needs ITPP_F64 coefficients");

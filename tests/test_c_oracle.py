@@ -58,3 +58,88 @@ def test_export_is_canonical_order():
     strs, coef = o.export()
     keys = [itpp.canonical_key(s) for s in strs]
     assert keys == sorted(keys)
+
+
+def _max_rel(a, b):
+    scale = max(1e-300, max(abs(float(v)) for v in b))
+    return max(abs(float(x) - float(y)) for x, y in zip(a, b)) / scale
+
+
+@pytest.mark.parametrize("builder,steps,obs", [
+    (lambda: W.tfim_workload("t", 10, 1.0, 0.9, True, 1, 0.05, 0.2, 1e-6, 300), 4, None),
+    (lambda: W.tfim_workload("t", 12, 0.8, 1.1, False, 2, 0.05, 0.15, 1e-7, 200), 3, "x0"),
+    (lambda: W.random_two_flip_workload("r", 12, 14, 1, 0.1, 2, 1e-9, 150), 2, None),
+])
+def test_reverse_sweep_matches_python_adjoint(builder, steps, obs):
+    """The C++ reverse sweep (frozen support) against the pinned Python
+    reverse-mode oracle: binding caps, thresholds, Y terms, Strang order."""
+    from oracle import adjoint as AD
+
+    w = builder()
+    if obs is None:
+        os_, oc = w.strings, [a / w.n for a in w.alphas]
+    else:
+        os_, oc = ["X" + "I" * (w.n - 1), w.strings[0]], [1.0, -0.5]
+    Lr, dar, ddr, dthr = AD.gradients(w, os_, oc, n_steps=steps)
+    o = c_oracle.COracle(w.n)
+    L, da, dd, dth = o.gradients(w, os_, oc, n_steps=steps)
+    assert len(dth) == len(dthr)
+    assert abs(L - Lr) <= 1e-14 * max(1.0, abs(Lr))
+    assert _max_rel(dth, dthr) <= 1e-13
+    assert _max_rel(da, dar) <= 1e-13
+    assert abs(dd - ddr) <= 1e-13 * max(1.0, abs(ddr))
+    # the forward part leaves the oracle's final state
+    S, _ = itpp.evolve(w.n, w.strings, w.alphas, w.schedule, w.dtau, steps, w.delta, w.K)
+    assert o.state() == S
+
+
+def test_reverse_sweep_h0_closed_form_n16():
+    """h = 0 open chain, untruncated, 2^15 strings: <H> = -J (n-1) tanh(beta J),
+    so d<H>/dbeta = -J^2 (n-1) sech^2(beta J) and the J derivative follows."""
+    n, J, beta = 16, 0.9, 0.6
+    w = W.tfim_workload("t", n, J, 0.0, False, 1, 0.05, beta, 0.0, 1 << 40)
+    o = c_oracle.COracle(n)
+    L, da, dd, _ = o.gradients(w, w.strings, w.alphas)
+    nzz = n - 1
+    t = math.tanh(beta * J)
+    sech2 = 1.0 - t * t
+    assert abs(L + J * nzz * t) < 1e-12
+    assert abs(dd / w.n_steps + J * J * nzz * sech2) < 1e-11
+    S = o.state()
+    zz = sum(S.get(w.strings[k], 0.0) for k in range(nzz))
+    dJ = -zz - sum(da[k] for k in range(nzz))
+    assert abs(dJ + nzz * (t + beta * J * sech2)) < 1e-11
+
+
+def test_reverse_sweep_from_loaded_state_matches_python():
+    from oracle import adjoint as AD
+
+    w = W.tfim_workload("t", 12, 1.0, 0.9, True, 1, 0.05, 1.0, 1e-9, 400)
+    x, z, c = W.synthetic_state_words(w.n, 300, seed=51, partner=w.strings[w.schedule[0][0]])
+    o = c_oracle.COracle(w.n)
+    o.load_words(x, z, c)
+    S0 = o.state()
+    obs = (w.strings, [a / w.n for a in w.alphas])
+    Lr, dar, ddr, dthr = AD.gradients(w, *obs, n_steps=2, S0=S0)
+    L, da, dd, dth = o.gradients(w, *obs, n_steps=2)
+    assert abs(L - Lr) <= 1e-14 * max(1.0, abs(Lr))
+    assert _max_rel(dth, dthr) <= 1e-13
+    assert abs(dd - ddr) <= 1e-13 * max(1.0, abs(ddr))
+
+
+@pytest.mark.parametrize("n", [12, 64, 100])
+def test_word_import_export_roundtrip(n):
+    x, z, c = W.synthetic_state_words(n, 500, seed=5)
+    o = c_oracle.COracle(n)
+    o.load_words(x, z, c)
+    S = o.state()
+    assert len(S) == len(c)
+    x2, z2, c2 = o.export_words(x.shape[1])
+    strs, coef = o.export()
+    assert np.array_equal(coef, c2)
+    for i in range(len(c2)):
+        assert itpp.canonical_key(strs[i]) == (sum(int(x2[i, q]) << (64 * q) for q in range(x.shape[1])),
+                                               sum(int(z2[i, q]) << (64 * q) for q in range(x.shape[1])))
+    # the same multiset as the input
+    order = np.lexsort(tuple(z[:, q] for q in range(x.shape[1])) + tuple(x[:, q] for q in range(x.shape[1])))
+    assert np.array_equal(x[order], x2) and np.array_equal(z[order], z2) and np.array_equal(c[order], c2)

@@ -12,6 +12,7 @@ import pytest
 
 import itpp_workloads as W
 from oracle import adjoint as AD
+from oracle import c_oracle
 from oracle import itpp as OR
 
 pytestmark = pytest.mark.gpu
@@ -63,6 +64,34 @@ def test_random_hamiltonians_match_oracle(n, terms, seed, K):
     obs = (w.strings[:3] + ["X" + "I" * (n - 1)], [0.7, -1.1, 0.4, 2.0])
     e = check_against_oracle(w, obs, 2, 1)
     e.close()
+
+
+@pytest.mark.parametrize("n,K", [(64, 1 << 15), (100, 1 << 14)])
+def test_reverse_sweep_many_tiles_matches_oracle(n, K):
+    """Periodic TFIM (the adjoint benchmark's model), J = h = 1, dtau = 0.02,
+    threshold 1e-6, two Trotter steps with the cap binding on every gate.
+    The gate kernel's tile is 4000 merged strings for one-word keys and 2000
+    for two-word keys, so an X gate's join (the whole state) spans 8 or more
+    tiles: the reverse kernel's look-back positions and its gather of
+    lambda' cross many tiles.  Compared with the C++ reverse sweep."""
+    w = W.tfim_workload("t", n, 1.0, 1.0, True, 1, 0.02, 0.04, 1e-6, K)
+    obs = (w.strings, [a / n for a in w.alphas])
+    print(f"reverse sweep n={n} K={K}", flush=True)
+    e, st, (L, da, dd, dth) = gpu_backward(w, obs, 2, 1)
+    assert st["cap_hit"] == 1 and st["n_terms"] == K
+    S = e.state()
+    e.close()
+    c_oracle.build(force=False)
+    o = c_oracle.COracle(n)
+    Lr, dar, ddr, dthr = o.gradients(w, *obs, n_steps=2)
+    assert o.state() == S
+    assert len(dth) == len(dthr) == st["n_gates"]
+    scale = max(abs(v) for v in dthr)
+    assert max(abs(a - b) for a, b in zip(dth, dthr)) <= TOL * scale
+    assert abs(L - Lr) <= 1e-13 * max(1.0, abs(Lr))
+    sa = max(1.0, max(abs(v) for v in dar))
+    assert max(abs(a - b) for a, b in zip(da, dar)) <= TOL * sa
+    assert abs(dd - ddr) <= TOL * max(1.0, abs(ddr))
 
 
 def test_checkpoint_interval_does_not_change_results():

@@ -12,7 +12,6 @@ import pytest
 
 import itpp_workloads as W
 from oracle import c_oracle
-from oracle import itpp as OR
 
 pytestmark = pytest.mark.gpu
 
@@ -139,90 +138,48 @@ def test_import_errors_keep_the_previous_state():
     e2.close()
 
 
-def _sorted_words(x, z):
-    o = np.lexsort((z[:, 0], x[:, 0]))
-    return o, x[o, 0], z[o, 0]
-
-
-def _lookup(xs, zs, order, qx, qz):
-    """Row of (qx, qz) in a state sorted by (x, z), or -1."""
-    lo = np.searchsorted(xs, qx, "left")
-    hi = np.searchsorted(xs, qx, "right")
-    for r in range(lo, hi):
-        if zs[r] == qz:
-            return int(order[r])
-    return -1
-
-
-@pytest.mark.parametrize("first_gate", [0, 63])
-def test_one_gate_on_a_synthetic_full_size_state(first_gate):
-    """The benchmark workload's Hamiltonian and cap (n = 64, K = 2^24), default
-    options, one gate (ZZ half-step or X gate) on a loaded synthetic state of K
-    strings whose magnitudes take 76 distinct values, so the cap cuts through
-    groups of equal values.
-    - Sampled outputs: the oracle computes each one from the generated state (Eq. ITPP_PropRules, normalised by the identity output).
-    - Sampled candidates: every output of a sampled input is kept exactly when its normalised magnitude is above the smallest kept one, and dropped when below (top-K with the cap binding).
-    """
+@pytest.mark.parametrize("first_gate,n_gates,margin", [(0, 1, None), (63, 1, None), (0, 2, 1.0)])
+def test_gates_on_a_synthetic_full_size_state(first_gate, n_gates, margin):
+    """The benchmark workload's Hamiltonian and cap (n = 64, K = 2^24), in the
+    launch configuration the benchmark times, applied to a loaded synthetic
+    state of K strings whose magnitudes take 76 distinct values, so the cap
+    cuts through groups of equal values and the canonical-key tie-break
+    decides which of them survive.  The whole exported state is compared bit
+    for bit with the oracle loaded with the same generated state: one ZZ
+    half-step, one X gate, and two gates with the speculative write
+    threshold at margin 1.0 (the second gate writes only outputs at or above
+    the K-th value predicted from the first)."""
     w = W.config2()
     n, K = w.n, w.K
     sched = w.schedule[first_gate:] + w.schedule[:first_gate]
-    k_term, mult = sched[0]
-    Q = w.strings[k_term]
-    theta = OR.gate_angle(w.alphas[k_term], mult, w.dtau)
-    ch, sh = math.cosh(theta), math.sinh(theta)
+    Q = w.strings[sched[0][0]]
     x0, z0, c0 = W.synthetic_state_words(n, K, seed=21 + first_gate, partner=Q)
-    qx, qz = W.string_words(Q)
-
+    print(f"full-size gates: first_gate={first_gate} n_gates={n_gates} margin={margin}", flush=True)
     e = engine(w, schedule=sched)
     e.set_timing(True)
+    if margin is not None:
+        e.set_option("spec_margin", margin)
     e.import_words(x0, z0, c0)
-    st = e.evolve_gates(w.dtau, 1)
+    st = e.evolve_gates(w.dtau, n_gates)
     x1, z1, c1 = e.export()
     e.close()
     assert st["n_terms"] == K and st["cap_hit"] == 1 and len(c1) == K
+    if margin is not None:
+        assert st["spec_gates"] >= 1
+        print(f"speculative gates {st['spec_gates']}, redone {st['spec_retries']}", flush=True)
 
-    o0, xs0, zs0 = _sorted_words(x0, z0)
-    o1, xs1, zs1 = _sorted_words(x1, z1)
+    o = c_oracle.COracle(n)
+    o.load_words(x0, z0, c0)
+    del x0, z0, c0
+    o.evolve(w.strings, w.alphas, sched[:n_gates], w.dtau, 1, w.delta, K)
+    xo, zo, co = o.export_words(1)
+    del o
+    assert xo.shape == x1.shape
+    assert np.array_equal(x1, xo) and np.array_equal(z1, zo)
+    assert np.array_equal(c1.view(np.uint64), co.view(np.uint64))
+    # the cap cut a group of equal magnitudes
+    a = np.abs(c1[1:])
+    kth = a.min()
+    assert int(np.count_nonzero(a == kth)) > 1
 
-    def value(Rx, Rz):
-        """Pre-normalisation coefficient of output R: contributions of R and QR."""
-        R = to_string([Rx], [Rz], n)
-        acc = None
-        for px, pz in ((Rx, Rz), (Rx ^ int(qx[0]), Rz ^ int(qz[0]))):
-            i = _lookup(xs0, zs0, o0, np.uint64(px), np.uint64(pz))
-            if i < 0:
-                continue
-            Pstr = to_string([px], [pz], n)
-            for Rs, v in OR.gate_contributions(Pstr, float(c0[i]), Q, ch, sh):
-                if Rs == R:
-                    acc = v if acc is None else acc + v
-        return acc
 
-    vI = value(0, 0)
-    assert vI is not None and vI > 0
-    rng = np.random.default_rng(99)
-    ident = int(np.flatnonzero((x1[:, 0] == 0) & (z1[:, 0] == 0))[0])
-    assert c1[ident] == 1.0
-    for i in rng.integers(0, K, size=2000):
-        v = value(int(x1[i, 0]), int(z1[i, 0]))
-        assert v is not None
-        assert c1[i] == v / vI, i
-
-    kth = float(np.min(np.abs(np.delete(c1, ident))))
-    checked = 0
-    for i in rng.integers(1, K, size=2000):
-        Pstr = to_string(x0[i], z0[i], n)
-        for Rs, _ in OR.gate_contributions(Pstr, float(c0[i]), Q, ch, sh):
-            Rx, Rz = OR.canonical_key(Rs)
-            v = value(Rx, Rz)
-            if v is None or Rx == 0 and Rz == 0:
-                continue
-            nv = abs(v) / vI
-            kept = _lookup(xs1, zs1, o1, np.uint64(Rx), np.uint64(Rz)) >= 0
-            if nv > kth:
-                assert kept, Rs
-                checked += 1
-            elif nv < kth:
-                assert not kept, Rs
-                checked += 1
-    assert checked > 1000

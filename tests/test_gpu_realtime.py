@@ -85,3 +85,24 @@ def test_real_time_conserves_the_l2_norm_and_switches_back():
     o.evolve(w.strings, w.alphas, w.schedule, 0.05, 1, 0.0, 1 << 20)
     assert e.state() == o.state()
     e.close()
+
+
+def test_real_time_many_tiles_matches_oracle():
+    """n = 64, K = 2^15, a loaded state of 30000 strings: an X gate's join
+    holds the whole state (7 or more tiles of the gate kernel), a ZZ gate's
+    two joins split it; six gates from X_0 on, the cap binding."""
+    w = W.config2(K=1 << 15)
+    sched = w.schedule[63:] + w.schedule[:63]
+    x, z, c = W.synthetic_state_words(w.n, 30000, seed=33, partner=w.strings[sched[0][0]])
+    S0 = {to_string(x[i], z[i], w.n): float(c[i]) for i in range(len(c))}
+    e = P.Engine(w.n, w.delta, w.K)
+    e.set_hamiltonian(w.strings, w.alphas)
+    e.set_schedule(sched)
+    e.load(S0)
+    e.set_option("real_time", 1)
+    st = e.evolve_gates(0.07, 6)
+    S, updates = RT.evolve_real(S0, w.strings, w.alphas, sched[:6], 0.07, 1, w.delta, w.K)
+    assert st["cap_hit"] == 1
+    assert e.state() == S
+    assert st["term_updates"] == updates
+    e.close()
