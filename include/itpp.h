@@ -197,6 +197,20 @@ itpp_status itpp_export(itpp_ctx ctx, int64_t capacity, uint64_t* x, uint64_t* z
 itpp_status itpp_expect_squared(itpp_ctx ctx, int32_t n_strings, const uint64_t* x, const uint64_t* z,
                                 const double* coef, double* value, double* purity);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as itpp_expect_squared, bit for bit, computed without any device or
+ * host allocation.  The observable words are staged, their tables built and
+ * the per-block partial sums kept in a fixed scratch area of the library
+ * (about 1.4 MiB per GPU, held until the process ends) instead of buffers
+ * allocated per call.  Limits: n_strings <= 4096 and at most 65536
+ * non-identity sites summed over the strings (ITPP_ERR_ARG beyond either).
+ * Every call on one GPU uses that GPU's single scratch area: calls that
+ * overlap on one GPU (other threads, other streams) race and must be
+ * serialised by the caller.  Host arrays; waits for the stream. */
+itpp_status itpp_expect_squared_noalloc(itpp_ctx ctx, int32_t n_strings, const uint64_t* x, const uint64_t* z,
+                                       const double* coef, double* value, double* purity);
+
 /* Device-pointer variants, for arrays that already live on the device (for
  * example torch tensors).  Both run on cfg.stream; the arrays must be ready
  * on that stream and stay valid until the work is done.

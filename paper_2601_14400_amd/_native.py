@@ -22,7 +22,7 @@ STATUS = {0: "ITPP_OK", 1: "ITPP_ERR_ARG", 2: "ITPP_ERR_OOM", 3: "ITPP_ERR_CAP",
 # Every entry point declared in include/itpp.h.
 EXPORTED = ["itpp_create", "itpp_destroy", "itpp_set_hamiltonian", "itpp_set_schedule",
             "itpp_reset", "itpp_import", "itpp_evolve", "itpp_evolve_gates", "itpp_expect", "itpp_num_terms", "itpp_export",
-            "itpp_expect_device", "itpp_export_device", "itpp_expect_squared",
+            "itpp_expect_device", "itpp_export_device", "itpp_expect_squared", "itpp_expect_squared_noalloc",
             "itpp_set_adjoint", "itpp_backward", "itpp_num_gates", "itpp_set_option", "itpp_set_timing", "itpp_get_timing",
             "itpp_batch_create", "itpp_batch_destroy", "itpp_batch_instance", "itpp_batch_set_workers",
             "itpp_batch_evolve", "itpp_batch_autotune", "itpp_batch_last_error",
@@ -88,6 +88,7 @@ def load_library(path: Optional[str] = None):
     lib.itpp_export.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(i64)]
     lib.itpp_expect_device.argtypes = [vp, i32, vp, vp, vp, vp]
     lib.itpp_expect_squared.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+    lib.itpp_expect_squared_noalloc.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     lib.itpp_export_device.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(i64)]
     lib.itpp_set_adjoint.argtypes = [vp, i32, i64]
     lib.itpp_backward.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(dbl), vp, ctypes.POINTER(dbl), vp, i64]
@@ -334,15 +335,18 @@ class Engine:
         k = int(n_out.value)
         return x[:k], z[:k], c[:k]
 
-    def expect_squared(self, strings: Sequence[str], coefs: Sequence[float]) -> Tuple[float, float]:
+    def expect_squared(self, strings: Sequence[str], coefs: Sequence[float],
+                       noalloc: bool = False) -> Tuple[float, float]:
         """(<O>_{2 tau}, purity) of the squared state, O = sum_j coefs[j] strings[j]
-        (Tr[(O rho) rho] / Tr[rho^2] and sum_P a_P^2)."""
+        (Tr[(O rho) rho] / Tr[rho^2] and sum_P a_P^2).  noalloc: through
+        itpp_expect_squared_noalloc (no allocation; library scratch)."""
         x, z = strings_to_words(strings, self.n)
         c = np.ascontiguousarray(coefs, dtype=np.float64)
         v = ctypes.c_double()
         p = ctypes.c_double()
-        self._check(self._lib.itpp_expect_squared(self._h, len(strings), x.ctypes.data, z.ctypes.data, c.ctypes.data,
-                                                  ctypes.byref(v), ctypes.byref(p)))
+        fn = self._lib.itpp_expect_squared_noalloc if noalloc else self._lib.itpp_expect_squared
+        self._check(fn(self._h, len(strings), x.ctypes.data, z.ctypes.data, c.ctypes.data,
+                       ctypes.byref(v), ctypes.byref(p)))
         return float(v.value), float(p.value)
 
     def expect_device(self, x, z, coef, out=None):

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -121,6 +122,60 @@ constexpr uint32_t kStatusClearEvery = 2048;
 // Host synchronisation period (gates) for the speculation check.
 constexpr int64_t kSyncEvery = 512;
 thread_local std::string g_create_error = "no error";
+
+// Device scratch of itpp_expect_squared_noalloc: the observable words and
+// weights it stages, the tables built from them, the per-block partial sums
+// and the two results.  One copy per GPU, shared by every call on that GPU.
+constexpr int32_t kSqMaxStrings = 4096;   // observable strings per call
+constexpr int64_t kSqMaxSupport = 65536;  // non-identity sites summed over the strings
+constexpr int kSqMaxGrid = 4096;          // blocks of the squared-state kernel
+constexpr uint64_t sq_align(uint64_t b) { return (b + 255) & ~255ull; }
+constexpr uint64_t kSqOffX = 0;
+constexpr uint64_t kSqOffZ = kSqOffX + sq_align(8ull * kMaxWords * kSqMaxStrings);
+constexpr uint64_t kSqOffOc = kSqOffZ + sq_align(8ull * kMaxWords * kSqMaxStrings);
+constexpr uint64_t kSqOffQ = kSqOffOc + sq_align(8ull * kSqMaxStrings);
+constexpr uint64_t kSqOffC = kSqOffQ + sq_align(8ull * kMaxKeyWords * kSqMaxStrings);
+constexpr uint64_t kSqOffSupOff = kSqOffC + sq_align(8ull * kMaxKeyWords * kSqMaxStrings);
+constexpr uint64_t kSqOffSupPos = kSqOffSupOff + sq_align(4ull * (kSqMaxStrings + 1));
+constexpr uint64_t kSqOffSupQ = kSqOffSupPos + sq_align(8ull * kSqMaxSupport);
+constexpr uint64_t kSqOffAq = kSqOffSupQ + sq_align(4ull * kSqMaxSupport);
+constexpr uint64_t kSqOffCoef = kSqOffAq + sq_align(4ull * kSqMaxStrings);
+constexpr uint64_t kSqOffPart = kSqOffCoef + sq_align(8ull * kSqMaxStrings);
+constexpr uint64_t kSqOffOut = kSqOffPart + sq_align(32ull * kSqMaxGrid);
+constexpr uint64_t kSqScratchBytes = kSqOffOut + 256;
+static_assert(kSqScratchBytes <= (2ull << 20), "squared-state scratch stays below 2 MiB");
+
+// In host code `scratch` only names the symbol; its device address on each
+// GPU comes from hipGetSymbolAddress (scratch_address).
+static __device__ __align__(256) unsigned char scratch[kSqScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, looked up once per device with
+// that device current.
+hipError_t scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) {
+      const hipError_t r = hipSetDevice(cur);
+      if (e == hipSuccess) e = r;
+    }
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return hipSuccess;
+}
 
 itpp_status create_fail(itpp_status s, const std::string& m) {
   g_create_error = m;
@@ -400,6 +455,11 @@ itpp_status device_props(int* dev, hipDeviceProp_t* prop) {
 // [arena, arena + arena_size); measured != NULL: only return the bytes needed.
 itpp_status create_impl(const itpp_config* cfg, int dev, const hipDeviceProp_t& prop, uint8_t* arena,
                         uint64_t arena_size, uint64_t* measured, itpp_ctx* out) {
+  if (!measured) {
+    void* sp = nullptr;
+    const hipError_t se = scratch_address(dev, &sp);
+    if (se != hipSuccess) return create_fail(ITPP_ERR_DEVICE, std::string("scratch address: ") + hipGetErrorString(se));
+  }
   itpp_ctx c = new (std::nothrow) itpp_ctx_s;
   if (!c) return ITPP_ERR_OOM;
   c->cfg = *cfg;
@@ -1186,6 +1246,78 @@ itpp_status itpp_expect_squared(itpp_ctx c, int32_t m, const uint64_t* x, const 
   HIP_TRY(c, launch_squared(c->NW, c->f32, c->side[c->cur], c->plan + c->par, c->filt + c->par, rp, ob, c->ctl,
                             bpart.as<double>(), bout.as<double>(), grid, c->stream));
   HIP_TRY(c, hipMemcpyAsync(res, bout.p, sizeof(res), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  itpp_status st = check_error(c);
+  if (st != ITPP_OK) return st;
+  *purity = res[1];
+  *value = res[0] / res[1];
+  return ITPP_OK;
+}
+
+itpp_status itpp_expect_squared_noalloc(itpp_ctx c, int32_t m, const uint64_t* x, const uint64_t* z,
+                                       const double* coef, double* value, double* purity) {
+  if (!c || !value || !purity) return ITPP_ERR_ARG;
+  if (m < 0 || (m > 0 && (!x || !z || !coef))) return fail(c, ITPP_ERR_ARG, "bad observable arrays");
+  if (m > kSqMaxStrings) return fail(c, ITPP_ERR_ARG, "more than 4096 observable strings (the scratch limit)");
+  if (!c->ready) return fail(c, ITPP_ERR_STATE, "no valid state (reset required)");
+  const int W = c->W, n = c->n;
+  int64_t support = 0;
+  for (int j = 0; j < m; ++j) {
+    if (!std::isfinite(coef[j])) return fail(c, ITPP_ERR_ARG, "non-finite observable weight");
+    for (int q = 0; q < W; ++q) {
+      const uint64_t xw = x[(size_t)j * W + q], zw = z[(size_t)j * W + q];
+      const int hi = n - 64 * q;
+      if (hi < 64) {
+        const uint64_t bad = hi <= 0 ? ~0ull : ~((1ull << hi) - 1ull);
+        if ((xw | zw) & bad) return fail(c, ITPP_ERR_ARG, "observable has bits at or above n_qubits");
+      }
+      support += __builtin_popcountll(xw | zw);
+    }
+  }
+  if (support > kSqMaxSupport)
+    return fail(c, ITPP_ERR_ARG, "observable strings have more than 65536 non-identity sites in total (the scratch limit)");
+  void* sp = nullptr;
+  {
+    const hipError_t e = scratch_address(c->device, &sp);
+    if (e != hipSuccess) return hip_fail(c, e, "scratch address");
+  }
+  uint8_t* base = static_cast<uint8_t*>(sp);
+  const int grid = std::min(c->cus * 4, kSqMaxGrid);
+  uint64_t* dx = reinterpret_cast<uint64_t*>(base + kSqOffX);
+  uint64_t* dz = reinterpret_cast<uint64_t*>(base + kSqOffZ);
+  double* doc = reinterpret_cast<double*>(base + kSqOffOc);
+  SqTables t{};
+  t.qmask = reinterpret_cast<uint64_t*>(base + kSqOffQ);
+  t.cmask = reinterpret_cast<uint64_t*>(base + kSqOffC);
+  t.sup_off = reinterpret_cast<int32_t*>(base + kSqOffSupOff);
+  t.sup_pos = reinterpret_cast<int32_t*>(base + kSqOffSupPos);
+  t.sup_q = reinterpret_cast<int32_t*>(base + kSqOffSupQ);
+  t.aq = reinterpret_cast<int32_t*>(base + kSqOffAq);
+  t.coef = reinterpret_cast<double*>(base + kSqOffCoef);
+  double* part = reinterpret_cast<double*>(base + kSqOffPart);
+  double* out = reinterpret_cast<double*>(base + kSqOffOut);
+  RepPos rp{};
+  rp.nbits = c->nbits;
+  for (int b = 0; b < c->nbits; ++b) rp.pos[b] = (uint8_t)c->pos[b];
+  if (m > 0) {
+    HIP_TRY(c, hipMemcpyAsync(dx, x, sizeof(uint64_t) * m * W, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(dz, z, sizeof(uint64_t) * m * W, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(doc, coef, sizeof(double) * m, hipMemcpyHostToDevice, c->stream));
+  }
+  HIP_TRY(c, launch_sq_tables(rp, n, W, c->NW, dx, dz, doc, m, t, c->stream));
+  SqObs ob{};
+  ob.m = m;
+  ob.qmask = t.qmask;
+  ob.cmask = t.cmask;
+  ob.sup_off = t.sup_off;
+  ob.sup_pos = t.sup_pos;
+  ob.sup_q = t.sup_q;
+  ob.aq = t.aq;
+  ob.coef = t.coef;
+  HIP_TRY(c, launch_squared(c->NW, c->f32, c->side[c->cur], c->plan + c->par, c->filt + c->par, rp, ob, c->ctl, part,
+                            out, grid, c->stream));
+  double res[2] = {0.0, 0.0};
+  HIP_TRY(c, hipMemcpyAsync(res, out, sizeof(res), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   itpp_status st = check_error(c);
   if (st != ITPP_OK) return st;

@@ -883,6 +883,62 @@ hipError_t launch_select(int nw, int f32, Side out, const Plan* plan_out, const 
   return hipGetLastError();
 }
 
+// Observable tables of the squared-state readout, built on the device: per
+// string j its flip mask (qmask), anticommutation mask (cmask) and support
+// entries in ascending qubit order, exactly as the host-built tables.
+__global__ __launch_bounds__(256) void sq_tables_kernel(RepPos rp, int n, int W, int NW, const uint64_t* x,
+                                                        const uint64_t* z, const double* oc, int32_t m,
+                                                        SqTables t) {
+  const int tid = threadIdx.x;
+  // support sizes, then their exclusive prefix (one thread: m is small)
+  for (int j = tid; j < m; j += blockDim.x) {
+    int cnt = 0;
+    for (int q = 0; q < W; ++q) cnt += __popcll(x[(size_t)j * W + q] | z[(size_t)j * W + q]);
+    t.sup_off[j + 1] = cnt;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    t.sup_off[0] = 0;
+    for (int j = 0; j < m; ++j) t.sup_off[j + 1] += t.sup_off[j];
+  }
+  __syncthreads();
+  for (int j = tid; j < m; j += blockDim.x) {
+    uint64_t qm[kMaxKeyWords] = {0, 0, 0, 0}, cm[kMaxKeyWords] = {0, 0, 0, 0};
+    int e = t.sup_off[j], aq = 0;
+    for (int i = 0; i < n; ++i) {
+      const int xi = (int)((x[(size_t)j * W + (i >> 6)] >> (i & 63)) & 1ull);
+      const int zi = (int)((z[(size_t)j * W + (i >> 6)] >> (i & 63)) & 1ull);
+      if (!xi && !zi) continue;
+      const int px = rp.pos[i], pz = rp.pos[n + i];
+      if (xi) {
+        qm[px >> 6] |= 1ull << (px & 63);
+        cm[pz >> 6] |= 1ull << (pz & 63);  // x_Q z_P
+      }
+      if (zi) {
+        qm[pz >> 6] |= 1ull << (pz & 63);
+        cm[px >> 6] |= 1ull << (px & 63);  // z_Q x_P
+      }
+      t.sup_pos[2 * e] = px;
+      t.sup_pos[2 * e + 1] = pz;
+      t.sup_q[e] = xi | (zi << 1);
+      aq += xi & zi;
+      ++e;
+    }
+    for (int q = 0; q < NW; ++q) {
+      t.qmask[(size_t)j * NW + q] = qm[q];
+      t.cmask[(size_t)j * NW + q] = cm[q];
+    }
+    t.aq[j] = aq & 3;
+    t.coef[j] = oc[j];
+  }
+}
+
+hipError_t launch_sq_tables(const RepPos& rp, int n, int W, int NW, const uint64_t* x, const uint64_t* z,
+                            const double* oc, int32_t m, SqTables t, hipStream_t st) {
+  hipLaunchKernelGGL(sq_tables_kernel, dim3(1), dim3(256), 0, st, rp, n, W, NW, x, z, oc, m, t);
+  return hipGetLastError();
+}
+
 hipError_t launch_squared(int nw, int f32, Side s, const Plan* plan, const Filter* filt, const RepPos& rp,
                           const SqObs& ob, Ctl* ctl, double* part, double* out, int grid, hipStream_t st) {
   ITPP_DISPATCH(nw, f32,

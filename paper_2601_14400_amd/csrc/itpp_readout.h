@@ -27,6 +27,25 @@ struct SqObs {
   const double* coef;
 };
 
+// Writable view of the same arrays, filled on the device by
+// launch_sq_tables from canonical observable words.
+struct SqTables {
+  uint64_t* qmask;
+  uint64_t* cmask;
+  int32_t* sup_off;
+  int32_t* sup_pos;
+  int32_t* sup_q;
+  int32_t* aq;
+  double* coef;
+};
+
+// Builds the tables of m observable strings (canonical words: W x words then
+// W z words per string at x + j*W, z + j*W; weights oc) for a stored state
+// whose canonical bit b sits at rep position rp.pos[b] (one workgroup; the
+// support entries of string j start at the sum of the supports before it).
+hipError_t launch_sq_tables(const RepPos& rp, int n, int W, int NW, const uint64_t* x, const uint64_t* z,
+                            const double* oc, int32_t m, SqTables t, hipStream_t st);
+
 // part: 4 doubles per block of the first kernel (numerator and purity, each
 // with its compensation); out: numerator and purity.
 hipError_t launch_squared(int nw, int f32, Side s, const Plan* plan, const Filter* filt, const RepPos& rp,
