@@ -92,13 +92,21 @@ def summarize_pmc(fetch_csv: str, write_csv: str):
         rows = read(path)
         items = sorted(rows.items())
         gate_ids = [d for d, (k, _) in items if "gate_kernel" in k and "true" not in k]
+        # a gate redone after a failed speculation leaves the rest of its
+        # host batch as launches that return at once: they read and write
+        # (almost) nothing and are not gates, so the bytes of every launch
+        # are summed and divided by the launches that did work
+        vals = sorted(rows[d][1] for d in gate_ids)
+        floor = 0.01 * vals[len(vals) // 2] if vals else 0.0
         gate = [rows[d][1] for d in gate_ids]
+        worked = sum(1 for v in gate if v > floor)
         # the copy dispatches after the last gate launch are the calibration:
         # three copies of COPY_BYTES
         tail = [v for d, (k, v) in items if "copyBuffer" in k and d > gate_ids[-1]]
         per_copy_kib = sum(tail) / 3.0
         factor = (COPY_BYTES / 1024.0) / per_copy_kib
-        out[name] = {"launches": len(gate), "mean_kib_per_launch": sum(gate) / max(1, len(gate)),
+        out[name] = {"launches": worked, "empty_launches": len(gate) - worked,
+                     "mean_kib_per_launch": sum(gate) / max(1, worked),
                      "copy_kib_per_256MiB": per_copy_kib, "factor": factor}
     bpl = (out["fetch"]["mean_kib_per_launch"] * out["fetch"]["factor"] +
            out["write"]["mean_kib_per_launch"] * out["write"]["factor"]) * 1024.0
@@ -517,10 +525,13 @@ def main():
                 if tot is None:
                     tot = dict(sk)
                 else:
-                    for key in ("n_gates", "term_updates", "alg_bytes", "spec_gates", "spec_retries"):
+                    for key in ("n_gates", "term_updates", "alg_bytes", "spec_gates", "spec_retries", "written"):
                         tot[key] += sk[key]
                     for key in ("n_terms", "c_identity", "cap_hit"):
                         tot[key] = sk[key]
+                    tot["c_I_min"] = min(tot["c_I_min"], sk["c_I_min"])
+                    tot["c_I_max"] = max(tot["c_I_max"], sk["c_I_max"])
+                    tot["kth_abs_min"] = min(tot["kth_abs_min"], sk["kth_abs_min"])
                 progress(f"trotter steps {w.n_steps * (k + 1) // 10}/{w.n_steps}")
             st = tot
         else:
@@ -572,6 +583,9 @@ def main():
                      "alg_bytes_per_launch": bytes_per_launch, "launches": tim["gate_launches"]},
         "detail": {"term_updates_per_step": st["term_updates"], "final_terms": st["n_terms"],
                    "gate_ms_total": tim["gate_ms"], "select_ms_total": tim["select_ms"],
+                   "spec_gates": st["spec_gates"], "spec_retries": st["spec_retries"],
+                   "written_per_gate_over_K": st["written"] / max(1, st["n_gates"]) / args.K,
+                   "c_I_range": [st["c_I_min"], st["c_I_max"]], "kth_abs_min": st["kth_abs_min"],
                    "observables": vals},
     }
     rec = measured_traffic()

@@ -92,6 +92,12 @@ typedef struct {
   double alg_bytes;      /* sum over gates of (strings in + strings out) * (16W + 8) */
   int64_t spec_gates;    /* gates that wrote only strings above a predicted cap margin */
   int64_t spec_retries;  /* of those, gates redone because the prediction was too high */
+  double written;        /* sum over the gates of the strings they stored (identity included;
+                            above the cap when speculating: the next gate drops the excess) */
+  double c_I_min;        /* smallest and largest identity coefficient before normalisation */
+  double c_I_max;        /*   over the gates (Sec. II.C normalisation) */
+  double kth_abs_min;    /* smallest K-th largest |c| (normalised) over the gates whose cap
+                            bound (K-truncation, Sec. II.C); +inf if none */
 } itpp_stats;
 
 /* Kernel timing gathered with HIP events on the context's stream while

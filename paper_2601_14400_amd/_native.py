@@ -41,7 +41,9 @@ class ItppStats(ctypes.Structure):
                 ("term_updates", ctypes.c_double), ("c_identity", ctypes.c_double),
                 ("cap_hit", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("alg_bytes", ctypes.c_double), ("spec_gates", ctypes.c_int64),
-                ("spec_retries", ctypes.c_int64)]
+                ("spec_retries", ctypes.c_int64), ("written", ctypes.c_double),
+                ("c_I_min", ctypes.c_double), ("c_I_max", ctypes.c_double),
+                ("kth_abs_min", ctypes.c_double)]
 
 
 class ItppTiming(ctypes.Structure):
@@ -296,7 +298,8 @@ class Engine:
     def _stats(st):
         return {"n_terms": st.n_terms, "n_gates": st.n_gates, "term_updates": st.term_updates,
                 "c_identity": st.c_identity, "cap_hit": st.cap_hit, "alg_bytes": st.alg_bytes,
-                "spec_gates": st.spec_gates, "spec_retries": st.spec_retries}
+                "spec_gates": st.spec_gates, "spec_retries": st.spec_retries, "written": st.written,
+                "c_I_min": st.c_I_min, "c_I_max": st.c_I_max, "kth_abs_min": st.kth_abs_min}
 
     def set_option(self, name: str, value: float):
         opt = {"speculation": 1, "spec_margin": 2, "gate_shape": 3, "real_time": 4}[name]

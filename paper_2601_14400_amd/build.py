@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libitpp.so")
-SOURCES = ["itpp_gate.hip", "itpp_kernels.hip", "itpp_api.hip"]
+SOURCES = ["itpp_gate.hip", "itpp_layer.hip", "itpp_kernels.hip", "itpp_api.hip"]
 
 # -ffp-contract=off keeps every multiply and add separately rounded (the
 # arithmetic must match the CPU reference bit for bit); packed FP32 VALU

@@ -12,6 +12,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -471,7 +472,7 @@ itpp_status create_impl(const itpp_config* cfg, int dev, const hipDeviceProp_t& 
   c->coef_bytes = c->f32 ? 4 : 8;
   // two-word keys run faster with two 512-thread workgroups per CU (their
   // larger keys leave fewer registers per thread at 1024 threads)
-  c->shape = c->NW == 4 ? 1 : 0;
+  c->shape = 1;
   c->stream = static_cast<hipStream_t>(cfg->stream);
   c->device = dev;
   c->cus = prop.multiProcessorCount;
@@ -833,6 +834,46 @@ static itpp_status build_gate(itpp_ctx c, int i, const std::vector<int>& pos, do
     const int q = pos1[t.F[k]];
     gp.qm1[q >> 6] |= 1ull << (q & 63);
   }
+  // packed rep positions and the phase table of the layer kernel
+  gp.mvpos = 0;
+  for (int m = 0; m < gp.w1; ++m) gp.mvpos |= (uint32_t)gp.mv[m] << (8 * m);
+  gp.fgpos = 0;
+  for (int b = 0; b < gp.w2; ++b) gp.fgpos |= (uint32_t)gp.fposg[b] << (8 * b);
+  for (int m = 0; m < gp.w1; ++m) gp.fgpos |= (uint32_t)gp.epos[m] << (16 + 8 * m);
+  gp.q1pos = 0;
+  for (int k = 0; k < gp.w; ++k) gp.q1pos |= (uint32_t)pos1[t.F[k]] << (8 * k);
+  uint32_t phflip = 0;
+  gp.phpos = 0;
+  for (int j = 0; j < t.nsup; ++j) {
+    gp.phpos |= (uint32_t)gp.px[j] << (16 * j);
+    gp.phpos |= (uint32_t)gp.pz[j] << (16 * j + 8);
+    if (gp.px[j] >= nbits - gp.w) phflip |= 1u << (2 * j);
+    if (gp.pz[j] >= nbits - gp.w) phflip |= 1u << (2 * j + 1);
+  }
+  // e mod 4 of Q P = i^e R for every pattern of (x, z) bits of P on the
+  // support of Q (Pauli algebra, the convention of phase_negative)
+  gp.etab = 0;
+  bool phase_needed = c->real_time;
+  for (uint32_t idx = 0; idx < 16; ++idx) {
+    int e = t.aQ, anti = 0;
+    bool valid = true;
+    for (int j = 0; j < 2; ++j) {
+      const int xp = (idx >> (2 * j)) & 1, zp = (idx >> (2 * j + 1)) & 1;
+      if (j >= t.nsup) {
+        if (xp || zp) valid = false;
+        continue;
+      }
+      const int qx = t.qx[j], qz = t.qz[j];
+      const int xr = xp ^ qx, zr = zp ^ qz;
+      e += (xp & zp) - (xr & zr) + 2 * (qz & xp);
+      anti += (xp & qz) ^ (zp & qx);
+    }
+    e &= 3;
+    gp.etab |= (uint32_t)e << (2 * idx);
+    if (valid && !(anti & 1) && e != 0) phase_needed = true;
+  }
+  const uint32_t nph = phase_needed ? (uint32_t)(2 * t.nsup) : 0u;
+  gp.lflags = (uint32_t)gp.ov | ((uint32_t)gp.ovf << 2) | ((uint32_t)gp.w2 << 4) | (nph << 6) | (phflip << 9);
   gp.tile = gate_tile(c->NW, shape);
   if (c->epoch % kStatusClearEvery == 0) HIP_TRY(c, launch_clear_status(c->status, c->status_cap, c->stream));
   gp.epoch = c->epoch;
@@ -842,6 +883,7 @@ static itpp_status build_gate(itpp_ctx c, int i, const std::vector<int>& pos, do
   gp.cap_elems = c->cap;
   gp.status_cap = c->status_cap;
   gp.spec = spec ? 1 : 0;
+  gp.spos = i < kRatioSlots ? i : -1;
   gp.spec_mult = c->spec_mult;
   gp.serial = c->serial++;
   for (int b = 0; b < nbits; ++b) gp.pos_in[b] = (uint8_t)pos[b];
@@ -871,13 +913,18 @@ static itpp_status enqueue_gate(itpp_ctx c, double dtau, bool spec) {
     HIP_TRY(c, next_event(c, &e2));
     HIP_TRY(c, hipEventRecord(e0, c->stream));
   }
-  HIP_TRY(c, (c->real_time ? launch_gate_rt : launch_gate)(c->NW, c->f32, c->shape, gp, c->side[in], c->side[out],
-                                                           c->plan + pin, c->plan + pout,
-                         c->filt + pin, c->ctl, c->status, c->part, c->cus * gate_wgs_per_cu(c->shape), c->stream));
+  if (c->shape == 2)
+    HIP_TRY(c, launch_layer(c->NW, c->f32, c->real_time, gp, c->side[in], c->side[out], c->plan + pin, c->plan + pout,
+                            c->filt + pin, c->ctl, c->status, c->part, c->cus, c->stream));
+  else
+    HIP_TRY(c, (c->real_time ? launch_gate_rt : launch_gate)(c->NW, c->f32, c->shape, gp, c->side[in], c->side[out],
+                                                             c->plan + pin, c->plan + pout, c->filt + pin, c->ctl,
+                                                             c->status, c->part, c->cus * gate_wgs_per_cu(c->shape),
+                                                             c->stream));
   if (c->timing) HIP_TRY(c, hipEventRecord(e1, c->stream));
   HIP_TRY(c, launch_select(c->NW, c->f32, c->side[out], c->plan + pout, c->filt + pin, c->filt + pout, c->plan + pin,
                            c->ctl, c->sel, rp, c->cfg.max_terms, c->cfg.cap_policy == ITPP_CAP_FAIL ? 1 : 0,
-                           gp.spec, gp.serial, c->cus * 4, c->stream));
+                           gp.spec, gp.spos, gp.serial, c->cus * 4, c->stream));
   if (c->timing) HIP_TRY(c, hipEventRecord(e2, c->stream));
   c->pos.swap(pos1);
   c->cur = out;
@@ -906,6 +953,14 @@ static itpp_status run_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stat
   if (h0.error) return check_error(c);
   const double tu0 = h0.term_updates;
   const double ae0 = h0.alg_elems;
+  const double we0 = h0.written_elems;
+  {
+    // restart the run's min / max statistics (three adjacent doubles)
+    static const double init[3] = {HUGE_VAL, 0.0, HUGE_VAL};
+    static_assert(offsetof(Ctl, cI_max) == offsetof(Ctl, cI_min) + 8 && offsetof(Ctl, kth_min) == offsetof(Ctl, cI_min) + 16,
+                  "adjacent statistics");
+    HIP_TRY(c, hipMemcpyAsync(&c->ctl->cI_min, init, sizeof(init), hipMemcpyHostToDevice, c->stream));
+  }
   const uint64_t g0 = h0.gates;
   const uint64_t sg0 = h0.spec_gates;
   const int G = (int)c->glist.size();
@@ -999,6 +1054,10 @@ static itpp_status run_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stat
     st->alg_bytes = (h.alg_elems - ae0) * (double)(8 * c->NW + c->coef_bytes);
     st->spec_gates = (int64_t)(h.spec_gates - sg0);
     st->spec_retries = retries;
+    st->written = h.written_elems - we0;
+    st->c_I_min = h.cI_min;
+    st->c_I_max = h.cI_max;
+    st->kth_abs_min = h.kth_min;
   }
   if (c->timing) {
     Ctl h{};
@@ -1021,7 +1080,7 @@ itpp_status itpp_set_option(itpp_ctx c, int32_t option, double value) {
       c->spec_mult = value;
       return ITPP_OK;
     case ITPP_OPT_GATE_SHAPE:
-      if (value != 0.0 && value != 1.0) return fail(c, ITPP_ERR_ARG, "gate shape must be 0 or 1");
+      if (value != 0.0 && value != 1.0 && value != 2.0) return fail(c, ITPP_ERR_ARG, "gate shape must be 0, 1 or 2");
       c->shape = (int)value;
       return ITPP_OK;
     case ITPP_OPT_REAL_TIME:

@@ -107,6 +107,54 @@ __device__ __forceinline__ Key<NW> move_top(const Key<NW>& k, int p, int nbits) 
   return r;
 }
 
+// Bit p (a uniform rep position) of a key.
+template <int NW>
+__device__ __forceinline__ uint32_t bit_at(const Key<NW>& k, uint32_t p) {
+  return (uint32_t)(word_at(k, (int)(p >> 6)) >> (p & 63u)) & 1u;
+}
+
+template <int NW>
+__device__ __forceinline__ void flip_at(Key<NW>& k, uint32_t p) {
+  const uint64_t m = 1ull << (p & 63u);
+  const int wi = (int)(p >> 6);
+#pragma unroll
+  for (int i = 0; i < NW; ++i) k.w[i] ^= (wi == i) ? m : 0ull;
+}
+
+// Move the bit at rep position p to the top position top; the bits above p
+// shift down by one.  b receives the bit.
+template <int NW>
+__device__ __forceinline__ Key<NW> move_bit(const Key<NW>& k, uint32_t p, uint32_t top, uint32_t& b) {
+  b = bit_at(k, p);
+  Key<NW> r;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    const uint32_t lo = 64u * (uint32_t)i;
+    const uint64_t lm = p >= lo + 64u ? ~0ull : (p <= lo ? 0ull : (1ull << (p - lo)) - 1ull);
+    const uint64_t s = (k.w[i] >> 1) | ((i + 1 < NW) ? (k.w[i + 1] << 63) : 0ull);
+    r.w[i] = (k.w[i] & lm) | (s & ~lm);
+  }
+  const uint64_t t = (uint64_t)b << (top & 63u);
+  const int twi = (int)(top >> 6);
+#pragma unroll
+  for (int i = 0; i < NW; ++i) r.w[i] |= (twi == i) ? t : 0ull;
+  return r;
+}
+
+// Count one output in the 16 (class, next-next class) bins, 16-bit fields.
+__device__ __forceinline__ void bin_add(uint64_t (&nb)[4], int bin) {
+  const uint64_t inc = 1ull << (16 * (bin & 3));
+  const int wsel = bin >> 2;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) nb[i] += (wsel == i) ? inc : 0ull;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
 template <int NW>
 __device__ __forceinline__ Key<NW> load_key(const Side& s, uint64_t i) {
   Key<NW> k;
@@ -185,6 +233,57 @@ __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e
 __device__ __forceinline__ int hist_bin(uint64_t bits) {
   const int64_t b = (int64_t)(bits >> kHistShift) - (int64_t)kHistBase;
   return b < 0 ? 0 : (b >= kHistBins ? kHistBins - 1 : (int)b);
+}
+
+// The K-th value a gate's output is expected to have (before the gate's own
+// normalisation): the previous gate's exact K-th value, normalised, times
+// the ratio recorded at this schedule position the last time it ran (the
+// K-th value drifts slowly with beta); 0 when there is no previous K-th
+// value.  raw receives the prediction without the ratio.
+__device__ inline double predicted_kth(const Filter& fin, int spos, const Ctl* ctl, double* raw,
+                                       bool* have_ratio = nullptr) {
+  if (have_ratio) *have_ratio = false;
+  if (!fin.ref_bits) {
+    if (raw) *raw = 0.0;
+    return 0.0;
+  }
+  const double pred = __longlong_as_double((long long)fin.ref_bits) / fin.cI;
+  if (raw) *raw = pred;
+  if (spos < 0) return pred;
+  const float r = ctl->kth_ratio[spos];
+  if (!(r > 0.f)) return pred;
+  if (have_ratio) *have_ratio = true;
+  return __dmul_rn(pred, (double)r);
+}
+
+// Whether a gate writes only the outputs above a margin below its predicted
+// K-th value: speculation is allowed, the cap bound after the previous gate,
+// and this schedule position has a recorded ratio (from the second capped
+// Trotter step on; before that the K-th value still moves fast).  The gate
+// kernels and select_decide take the same decision.
+__device__ inline bool gate_speculates(const Filter& fin, int spec, int spos, const Ctl* ctl) {
+  bool have_ratio = false;
+  (void)predicted_kth(fin, spos, ctl, nullptr, &have_ratio);
+  return spec && fin.cap_active && have_ratio;
+}
+
+// Fine-histogram window around the predicted K-th value, and the write
+// threshold: delta, raised to a margin below the prediction when the gate
+// speculates.
+__device__ inline void gate_window(const Filter& fin, const GateParams& gp, const Ctl* ctl, uint64_t& win_lo,
+                                   uint64_t& win_hi, double& tw) {
+  win_lo = win_hi = 0;
+  tw = gp.delta;
+  const double pred = predicted_kth(fin, gp.spos, ctl, nullptr);
+  if (pred > 0.0) {
+    const uint64_t cb = abs_bits(pred);
+    win_lo = cb > kFineHalf ? cb - kFineHalf : 0;
+    win_hi = win_lo + 2 * kFineHalf;
+    if (gate_speculates(fin, gp.spec, gp.spos, ctl)) {
+      const double t = __dmul_rn(pred, gp.spec_mult);
+      tw = t > tw ? t : tw;
+    }
+  }
 }
 
 // Survivor test of a stored element under the filter decided after the gate

@@ -344,19 +344,11 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
   const int ncls = 1 << w;
   const int full = ncls - 1;
   const int ncls1 = 1 << gp.w1;
-  // fine histogram window around the value predicted from the previous cap
-  uint64_t win_lo = 0, win_hi = 0;
-  double tw = gp.delta;  // outputs are written when |v| > tw
-  if (fin.ref_bits) {
-    const double pred = __longlong_as_double((long long)fin.ref_bits) / fin.cI;
-    const uint64_t cb = abs_bits(pred);
-    win_lo = cb > kFineHalf ? cb - kFineHalf : 0;
-    win_hi = win_lo + 2 * kFineHalf;
-    if (gp.spec && fin.cap_active) {
-      const double t = __dmul_rn(pred, gp.spec_mult);
-      tw = t > tw ? t : tw;
-    }
-  }
+  // fine histogram window around the predicted K-th value; outputs are
+  // written when |v| > tw
+  uint64_t win_lo, win_hi;
+  double tw;
+  gate_window(fin, gp, ctl, win_lo, win_hi, tw);
 
   for (int i = tid; i < kFineBins; i += BLOCK) sm.fhist[i] = 0;
   if (tid < kMaxClasses * kMaxClasses) sm.ncnt[tid] = 0;
@@ -714,8 +706,7 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
           for (int q = 0; q < NQ; ++q)
             __hip_atomic_store(&status[(2 + q) * SN + t], tag32 | (excl[q] + agg[q]), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-          __atomic_thread_fence(__ATOMIC_RELEASE);
-#pragma unroll
+    #pragma unroll
           for (int sd = 0; sd < 2; ++sd)
             __hip_atomic_store(&status[sd * SN + t], aw[sd] | kInclReady, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -743,8 +734,9 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
         const uint16_t inf = sm.info[x];
         if (!(inf & (8u | 64u))) continue;
         const Key<NW> k = lds_key<NW, TILE>(sm.key, x);
-        Key<NW> mk = k;
-        for (int mm = 0; mm < gp.w1; ++mm) mk = move_top(mk, gp.mv[mm], nbits);
+        uint32_t bb;
+        Key<NW> mk = move_bit(k, gp.mvpos & 0xffu, (uint32_t)nbits - 1u, bb);
+        if (gp.w1 > 1) mk = move_bit(mk, (gp.mvpos >> 8) & 0xffu, (uint32_t)nbits - 1u, bb);
         const Key<NW> ownk = x < nAt ? k : xor_top(k, nbits, w);
         int fself = 0;
         for (int bq = 0; bq < gp.w2; ++bq) fself |= get_bit(ownk, gp.fposg[bq]) << bq;
@@ -769,6 +761,7 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
     }
     // (4) write outputs
     uint32_t written = 0, above = 0;
+    uint64_t nb[4] = {0, 0, 0, 0};  // (next class, next-next class) counts, 16-bit fields
     for (int x = tid; x < nt; x += BLOCK) {
       const uint16_t inf = sm.info[x];
       if (!(inf & (8u | 64u))) continue;
@@ -803,7 +796,7 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
             else if (bits >= win_lo) atomicAdd(&sm.fhist[(bits - win_lo) >> kFineShift], 1u);
             ++written;
           }
-          atomicAdd(&sm.ncnt[es * kMaxClasses + fself], 1u);
+          bin_add(nb, es * kMaxClasses + fself);
         }
       }
       if (inf & 64u) {
@@ -821,12 +814,24 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
           if (bits >= win_hi) ++above;
           else if (bits >= win_lo) atomicAdd(&sm.fhist[(bits - win_lo) >> kFineShift], 1u);
           ++written;
-          atomicAdd(&sm.ncnt[eb * kMaxClasses + (fself ^ gp.ovf)], 1u);
+          bin_add(nb, eb * kMaxClasses + (fself ^ gp.ovf));
         }
       }
     }
     if (written) atomicAdd(&sm.nwritten, written);
     if (above) atomicAdd(&sm.nabove, above);
+    // the tile's class counts: one sum per wavefront, one LDS add per bin
+    if (__ballot((nb[0] | nb[1] | nb[2] | nb[3]) != 0) != 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) nb[i] = wave_sum_u64(nb[i]);
+      if (lane < kMaxClasses * kMaxClasses) {
+        uint64_t v = nb[0];
+#pragma unroll
+        for (int i = 1; i < 4; ++i) v = ((lane >> 2) == i) ? nb[i] : v;
+        const uint32_t cnt = (uint32_t)((v >> (16 * (lane & 3))) & 0xffffull);
+        if (cnt) atomicAdd(&sm.ncnt[lane], cnt);
+      }
+    }
     // the next ticket is taken only once this tile's work is done, so tiles
     // start in ticket order (the look-back relies on it); t and the bounds
     // were read into registers at the top of this tile
@@ -885,10 +890,11 @@ struct GateShape<1> {
 };
 
 int gate_tile(int nw, int shape) {
+  if (shape == 2) return layer_tile();
   if (shape == 1) return nw == 2 ? GateShape<1>::tile<2>() : GateShape<1>::tile<4>();
   return nw == 2 ? GateShape<0>::tile<2>() : GateShape<0>::tile<4>();
 }
-int gate_min_tile(int nw) { return std::min(gate_tile(nw, 0), gate_tile(nw, 1)); }
+int gate_min_tile(int nw) { return std::min(std::min(gate_tile(nw, 0), gate_tile(nw, 1)), gate_tile(nw, 2)); }
 int gate_wgs_per_cu(int shape) { return shape == 1 ? GateShape<1>::wgs_per_cu : GateShape<0>::wgs_per_cu; }
 
 hipError_t launch_partition(int nw, const GateParams& gp, Side in, const Plan* plan_in, Ctl* ctl, uint64_t* part,

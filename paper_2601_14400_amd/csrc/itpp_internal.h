@@ -32,6 +32,7 @@ constexpr uint32_t kHistBase = (1023u - 62u) << 4;  // bin 0 starts at 2^-62
 constexpr int kFineBins = 1024;              // fine |c| histogram around the predicted K-th value
 constexpr int kFineShift = 38;               // bin width 2^38 ulps of the f64 pattern
 constexpr uint64_t kFineHalf = 1ull << 47;   // window half width (~2.2% relative)
+constexpr int kRatioSlots = 1024;            // schedule positions with a recorded K-th value ratio
 
 // Description of a stored state (written by the gate that produced it).
 struct Plan {
@@ -81,6 +82,13 @@ struct Ctl {
   uint32_t halt;             // 1: a speculative gate must be redone; later kernels do nothing
   uint64_t halt_serial;      // serial of that gate
   uint64_t spec_gates;       // gates that ran with a speculative write threshold
+  double written_elems;      // sum over gates of the strings stored (identity included)
+  // over the gates since the host last set them (run statistics):
+  double cI_min, cI_max;     // identity coefficient before normalisation
+  double kth_min;            // smallest normalised K-th |c| of a gate whose cap bound
+  // per schedule position: the exact K-th value of the gate's output over the
+  // value predicted from its input (the last time that position ran; 0: none)
+  float kth_ratio[kRatioSlots];
 };
 
 enum : uint32_t {
@@ -137,6 +145,7 @@ struct GateParams {
   int32_t fposg[kMaxClassBits];  // positions, in this rep, of the flip bits of the gate after next
   int32_t ovf;               // pattern over the latter bits flipped by this gate
   int32_t spec;              // 1: write only outputs above a margin below the predicted K-th value
+  int32_t spos;              // schedule position (index of kth_ratio), -1: none
   uint64_t qm1[kMaxKeyWords];    // this gate's flip mask in the next rep (branch key = self key ^ qm1)
   double spec_mult;          // that margin as a factor of the predicted value
   uint64_t serial;           // host serial number of this gate launch
@@ -146,6 +155,14 @@ struct GateParams {
   double delta;              // keep |c| > delta
   uint64_t cap_elems;        // capacity of each side in elements
   uint64_t status_cap;       // entries of the look-back status array
+  // Rep positions packed one per byte, for the layer kernel (computed once
+  // per gate on the host):
+  uint32_t mvpos;    // mv[0] | mv[1] << 8 (sequential positions of the next gate's flip bits)
+  uint32_t fgpos;    // fposg[0] | fposg[1] << 8 | epos[0] << 16 | epos[1] << 24
+  uint32_t phpos;    // x_j0 | z_j0 << 8 | x_j1 << 16 | z_j1 << 24 (support of Q, current rep)
+  uint32_t q1pos;    // this gate's flip bits in the next rep (w bytes)
+  uint32_t etab;     // e mod 4 of Q P = i^e R for the 16 patterns of the phase bits (2 bits each)
+  uint32_t lflags;   // ov | ovf << 2 | w2 << 4 | nph << 6 | phflip << 9
   uint8_t pos_in[kMaxBits];  // canonical bit -> rep position of the stored (input) keys
 };
 
@@ -183,7 +200,7 @@ hipError_t launch_gate_rt(int nw, int f32, int shape, const GateParams& gp, Side
                        int grid, hipStream_t st);
 hipError_t launch_select(int nw, int f32, Side out, const Plan* plan_out, const Filter* filt_in,
                          Filter* filt_out, Plan* plan_next, Ctl* ctl, SelBuf sel, const RepPos& rp,
-                         int64_t K, int cap_fail, int spec, uint64_t serial, int grid, hipStream_t st);
+                         int64_t K, int cap_fail, int spec, int spos, uint64_t serial, int grid, hipStream_t st);
 hipError_t launch_prepare(Plan* plan_out, Ctl* ctl, hipStream_t st);
 hipError_t launch_adjoint_gate(int nw, const GateParams& gp, Side in, const Plan* plan_in, Plan* plan_scratch,
                                const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part,
@@ -201,6 +218,12 @@ hipError_t launch_observe(int nw, int f32, Side s, const Plan* plan, const Filte
 hipError_t launch_export(int nw, int f32, Side s, const Plan* plan, const Filter* filt, const RepPos& rp,
                          uint64_t* ex, uint64_t* ez, double* ec, unsigned long long* count,
                          uint64_t limit, int grid, hipStream_t st);
+// The layer kernel (itpp_layer.hip): the forward gate with small workgroups,
+// several per CU (see launch_layer).
+hipError_t launch_layer(int nw, int f32, bool rt, const GateParams& gp, Side in, Side out, const Plan* plan_in,
+                        Plan* plan_out, const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part, int cus,
+                        hipStream_t st);
+int layer_tile();
 int gate_tile(int nw, int shape);
 int gate_min_tile(int nw);
 int gate_wgs_per_cu(int shape);

@@ -80,7 +80,7 @@ __device__ inline void find_from_top(const uint32_t* h, int nbins, uint64_t base
 // binds and which bit range of |c| holds the (K-1)-th largest non-identity
 // value; prepare the control block for the next gate.
 __global__ __launch_bounds__(1024) void select_decide(const Filter* filt_in, Filter* filt_out, Plan* plan_next,
-                                                      Ctl* ctl, int64_t K, int cap_fail, int spec,
+                                                      Ctl* ctl, int64_t K, int cap_fail, int spec, int spos,
                                                       uint64_t serial) {
   __shared__ uint32_t fh[kFineBins];
   __shared__ uint64_t scr[1024];
@@ -88,11 +88,12 @@ __global__ __launch_bounds__(1024) void select_decide(const Filter* filt_in, Fil
   __shared__ uint64_t s_above;
   const int tid = threadIdx.x;
   if (ctl->error || ctl->halt) return;
+  // the decision the gate kernel took
+  const bool specd = gate_speculates(*filt_in, spec, spos, ctl);
   {
     // a speculative gate that wrote fewer than K-1 strings above its write
     // threshold cannot decide the cap exactly: ask the host to redo it
-    const Filter& f0 = *filt_in;
-    if (spec && f0.cap_active && (int64_t)ctl->n_written_nonid < K - 1) {
+    if (specd && (int64_t)ctl->n_written_nonid < K - 1) {
       __syncthreads();
       if (tid == 0) {
         ctl->halt = 1u;
@@ -109,16 +110,20 @@ __global__ __launch_bounds__(1024) void select_decide(const Filter* filt_in, Fil
   __syncthreads();
   const Filter fin = *filt_in;
   const uint64_t nw = ctl->n_written_nonid + 1;  // identity included
-  const bool capped = (int64_t)nw > K;
+  // A speculative gate that stored exactly K strings stored the K largest
+  // outputs (the ones it skipped are below its write threshold, hence below
+  // every stored one): the cap binds at the smallest stored value.
+  const bool capped = (int64_t)nw > K || (specd && (int64_t)nw == K);
   const uint64_t need = (uint64_t)(K - 1);
   uint64_t sel_lo = 0, sel_hi = 0, sel_need = 0;
   bool none_kept = false, coarse = false;
   if (capped && need == 0) {
     none_kept = true;
   } else if (capped) {
+    // the window the gate kernel histogrammed (the same prediction)
     uint64_t win_lo = 0, win_hi = 0;
-    if (fin.ref_bits) {
-      const double pred = __longlong_as_double((long long)fin.ref_bits) / fin.cI;
+    const double pred = predicted_kth(fin, spos, ctl, nullptr);
+    if (pred > 0.0) {
       const uint64_t cb = abs_bits(pred);
       win_lo = cb > kFineHalf ? cb - kFineHalf : 0;
       win_hi = win_lo + 2 * kFineHalf;
@@ -164,9 +169,14 @@ __global__ __launch_bounds__(1024) void select_decide(const Filter* filt_in, Fil
     if (!capped && fin.ref_bits) f.ref_bits = abs_bits(__longlong_as_double((long long)fin.ref_bits) / fin.cI);
     *filt_out = f;
     ctl->term_updates += (double)fin.n_survivors;
+    ctl->written_elems += (double)nw;
+    if (ctl->have_cI) {
+      ctl->cI_min = cI < ctl->cI_min ? cI : ctl->cI_min;
+      ctl->cI_max = cI > ctl->cI_max ? cI : ctl->cI_max;
+    }
     ctl->alg_elems += (double)fin.n_survivors + (double)f.n_survivors;
     ctl->gates += 1;
-    if (spec && fin.cap_active) ctl->spec_gates += 1;
+    if (specd) ctl->spec_gates += 1;
     if (capped) ctl->cap_hit = 1;
     ctl->sel_lo = sel_lo;
     ctl->sel_hi = sel_hi;
@@ -322,8 +332,8 @@ __global__ void select_collect(Side out, const Plan* plan, Ctl* ctl, SelBuf sel)
 // Exact K-th value among the candidates (radix select on the |c| bits) and,
 // for ties at that value, the largest canonical key still kept.
 template <int NW>
-__global__ __launch_bounds__(1024) void select_exact(Side out, Filter* filt_out, Ctl* ctl, SelBuf sel,
-                                                     RepPos rp) {
+__global__ __launch_bounds__(1024) void select_exact(Side out, const Filter* filt_in, Filter* filt_out, Ctl* ctl,
+                                                     SelBuf sel, RepPos rp, int spos) {
   __shared__ uint32_t h[2048];
   __shared__ uint64_t scr[1024];
   __shared__ int s_bin;
@@ -406,6 +416,12 @@ __global__ __launch_bounds__(1024) void select_exact(Side out, Filter* filt_out,
     filt_out->ref_bits = kth;
     filt_out->tie_active = 0;
     s_ntie = 0;
+    // how far the K-th value moved from the raw prediction at this position
+    double raw = 0.0;
+    (void)predicted_kth(*filt_in, -1, ctl, &raw);
+    if (spos >= 0 && raw > 0.0) ctl->kth_ratio[spos] = (float)(__longlong_as_double((long long)kth) / raw);
+    const double kn = __longlong_as_double((long long)kth) / filt_out->cI;
+    if (kn < ctl->kth_min) ctl->kth_min = kn;
   }
   __syncthreads();
   if (count_eq <= need_eq) return;
@@ -871,14 +887,14 @@ hipError_t launch_prepare(Plan* plan_out, Ctl* ctl, hipStream_t st) {
 
 hipError_t launch_select(int nw, int f32, Side out, const Plan* plan_out, const Filter* filt_in,
                          Filter* filt_out, Plan* plan_next, Ctl* ctl, SelBuf sel, const RepPos& rp,
-                         int64_t K, int cap_fail, int spec, uint64_t serial, int grid, hipStream_t st) {
+                         int64_t K, int cap_fail, int spec, int spos, uint64_t serial, int grid, hipStream_t st) {
   hipLaunchKernelGGL(select_decide, dim3(1), dim3(1024), 0, st, filt_in, filt_out, plan_next, ctl, K,
-                     cap_fail, spec, serial);
+                     cap_fail, spec, spos, serial);
   ITPP_DISPATCH(nw, f32, {
     hipLaunchKernelGGL((select_coarse_hist<NWC, TC>), dim3(grid / 4 > 0 ? grid / 4 : 1), dim3(256), 0, st, out,
                        plan_out, ctl);
     hipLaunchKernelGGL((select_collect<NWC, TC>), dim3(grid), dim3(256), 0, st, out, plan_out, ctl, sel);
-    hipLaunchKernelGGL(select_exact<NWC>, dim3(1), dim3(1024), 0, st, out, filt_out, ctl, sel, rp);
+    hipLaunchKernelGGL(select_exact<NWC>, dim3(1), dim3(1024), 0, st, out, filt_in, filt_out, ctl, sel, rp, spos);
   });
   return hipGetLastError();
 }

@@ -53,6 +53,22 @@ def test_summarize_scales_by_the_copy_calibration(tmp_path, monkeypatch):
     assert rec["kernel_source_sha256"] == bench.kernel_source_hash()
 
 
+def test_summarize_counts_only_launches_that_did_work(tmp_path, monkeypatch):
+    """A redone gate leaves launches that return at once (a few bytes): they
+    are not gates and do not dilute the per-launch traffic."""
+    rec_path = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "TRAFFIC_RECORD", str(rec_path))
+    f = tmp_path / "fetch.csv"
+    w = tmp_path / "write.csv"
+    true_kib = bench.COPY_BYTES / 1024.0
+    _write_counters(f, "FETCH_SIZE", [1000.0, 0.25, 3000.0, 0.5], true_kib / 2)
+    _write_counters(w, "WRITE_SIZE", [500.0, 0.0, 1500.0, 0.0], true_kib)
+    bench.summarize_pmc(str(f), str(w))
+    rec = json.load(open(rec_path))
+    assert rec["counters"]["fetch"]["launches"] == 2 and rec["counters"]["fetch"]["empty_launches"] == 2
+    assert rec["bytes_per_launch"] == pytest.approx((4000.75 / 2 * 2.0 + 1000.0) * 1024.0)
+
+
 def test_record_ignored_for_another_kernel_source(tmp_path, monkeypatch):
     rec_path = tmp_path / "traffic.json"
     monkeypatch.setattr(bench, "TRAFFIC_RECORD", str(rec_path))
