@@ -98,6 +98,8 @@ typedef struct {
   double c_I_max;        /*   over the gates (Sec. II.C normalisation) */
   double kth_abs_min;    /* smallest K-th largest |c| (normalised) over the gates whose cap
                             bound (K-truncation, Sec. II.C); +inf if none */
+  int64_t graph_steps;   /* Trotter steps of this call run as replays of a recorded
+                            step graph (ITPP_OPT_GRAPHS) */
 } itpp_stats;
 
 /* Kernel timing gathered with HIP events on the context's stream while
@@ -293,12 +295,27 @@ itpp_status itpp_num_gates(itpp_ctx ctx, int64_t* out);
  *    cos(theta) P + i sin(theta) Q P (real: i Q P = -+R).  Truncation is
  *    unchanged; the identity coefficient stays 1.  Start from a state given
  *    by itpp_import (rho = I does not move).  Disables the reverse sweep of
- *    the run. */
+ *    the run.
+ *  ITPP_OPT_GRAPHS (default 1): run whole Trotter steps as replays of a HIP
+ *    graph recorded from the context's own launches.  From the second step
+ *    on every step starts from the same bit order of the stored keys, so
+ *    its launches are the same; the library records them once (stream
+ *    capture) and replays them (two steps per graph where a step has an
+ *    odd number of non-identity gates).  Used only with speculation on, no
+ *    forward checkpoints (itpp_set_adjoint) and no event timing
+ *    (itpp_set_timing).
+ *    The null stream cannot be captured: with cfg.stream == NULL the gates
+ *    of an itpp_evolve run on a private non-blocking stream that waits for
+ *    the null stream's earlier work and that the null stream then waits
+ *    for, so the ordering seen by the caller is unchanged.  Results are
+ *    bit-identical with and without graphs.  Changing an option, the
+ *    Hamiltonian or the schedule drops the recorded graph. */
 typedef enum {
   ITPP_OPT_SPECULATION = 1,
   ITPP_OPT_SPEC_MARGIN = 2,
   ITPP_OPT_GATE_SHAPE = 3,
-  ITPP_OPT_REAL_TIME = 4
+  ITPP_OPT_REAL_TIME = 4,
+  ITPP_OPT_GRAPHS = 5
 } itpp_option;
 itpp_status itpp_set_option(itpp_ctx ctx, int32_t option, double value);
 

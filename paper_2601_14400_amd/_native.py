@@ -43,7 +43,7 @@ class ItppStats(ctypes.Structure):
                 ("alg_bytes", ctypes.c_double), ("spec_gates", ctypes.c_int64),
                 ("spec_retries", ctypes.c_int64), ("written", ctypes.c_double),
                 ("c_I_min", ctypes.c_double), ("c_I_max", ctypes.c_double),
-                ("kth_abs_min", ctypes.c_double)]
+                ("kth_abs_min", ctypes.c_double), ("graph_steps", ctypes.c_int64)]
 
 
 class ItppTiming(ctypes.Structure):
@@ -299,10 +299,11 @@ class Engine:
         return {"n_terms": st.n_terms, "n_gates": st.n_gates, "term_updates": st.term_updates,
                 "c_identity": st.c_identity, "cap_hit": st.cap_hit, "alg_bytes": st.alg_bytes,
                 "spec_gates": st.spec_gates, "spec_retries": st.spec_retries, "written": st.written,
-                "c_I_min": st.c_I_min, "c_I_max": st.c_I_max, "kth_abs_min": st.kth_abs_min}
+                "c_I_min": st.c_I_min, "c_I_max": st.c_I_max, "kth_abs_min": st.kth_abs_min,
+                "graph_steps": st.graph_steps}
 
     def set_option(self, name: str, value: float):
-        opt = {"speculation": 1, "spec_margin": 2, "gate_shape": 3, "real_time": 4}[name]
+        opt = {"speculation": 1, "spec_margin": 2, "gate_shape": 3, "real_time": 4, "graphs": 5}[name]
         self._check(self._lib.itpp_set_option(self._h, opt, float(value)))
 
     def set_timing(self, enable: bool = True):

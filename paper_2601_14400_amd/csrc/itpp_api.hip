@@ -41,6 +41,14 @@ struct TermInfo {
   int aQ = 0;
 };
 
+// Host state before one enqueued gate (to redo a speculative gate).
+struct HostSnap {
+  std::vector<int> pos;
+  int cur, par, gpos;
+  uint64_t serial;
+  size_t ev_used;
+};
+
 // A stored state in the packed layout (regions back to back), with the
 // host data needed to continue the schedule from it.
 struct Snapshot {
@@ -92,8 +100,7 @@ struct itpp_ctx_s {
   int gpos = 0;          // index in glist of the next gate to apply
   int par = 0;           // plan/filter slot describing the stored state
   bool ready = false;
-  uint32_t epoch = 1;
-  uint64_t serial = 1;
+  uint64_t serial = 0;  // the device's gate serial of the next enqueued gate (mirror)
   bool speculate = true;
   bool real_time = false;       // gates follow the real-time rule (ITPP_OPT_REAL_TIME)
   double spec_mult = 0.98;
@@ -112,14 +119,29 @@ struct itpp_ctx_s {
   double fwd_dtau = 0.0;        // their common dtau
   bool fwd_valid = true;        // false once the gates since reset cannot be replayed
   std::vector<Snapshot> ckpts;  // forward checkpoints
+  // Recorded graph of one Trotter step.  The bit order of the stored keys
+  // at the start of a step is the same from the second step on (every step
+  // moves the same bits in the same order), so the launches of a step,
+  // whose arguments depend only on that order, dtau and the options, are
+  // recorded once and replayed.
+  bool graphs = true;                // ITPP_OPT_GRAPHS
+  hipGraphExec_t step_exec = nullptr;
+  std::vector<int> step_pos;         // bit order at the start of the recorded step
+  int step_cur = -1, step_par = -1;  // ping-pong slots it starts from
+  double step_dtau = 0.0;
+  std::vector<HostSnap> step_snaps;  // host state before each of its gates (serial relative)
+  std::vector<int> last_step_pos;    // bit order at the start of the previous step
+  int64_t graph_steps = 0;           // steps run as graph replays (statistics)
+  // The null stream cannot be captured: with cfg.stream == NULL the gates
+  // run on a private non-blocking stream joined to the null stream by events
+  // before and after (so they stay ordered with the caller's work).
+  hipStream_t gate_stream = nullptr;
+  hipEvent_t join_in = nullptr, join_out = nullptr;
 };
 
 namespace {
 
 const char* kVersion = "itpp gfx950 merge-join engine 0.2";
-// The look-back records carry 12-bit epoch tags that repeat every 4095
-// gates: clear them every 2048 gates.
-constexpr uint32_t kStatusClearEvery = 2048;
 // Host synchronisation period (gates) for the speculation check.
 constexpr int64_t kSyncEvery = 512;
 thread_local std::string g_create_error = "no error";
@@ -544,6 +566,8 @@ itpp_status create_impl(const itpp_config* cfg, int dev, const hipDeviceProp_t& 
 
 }  // namespace
 
+static void drop_step_graph(itpp_ctx c);
+
 extern "C" {
 
 itpp_status itpp_create(const itpp_config* cfg, itpp_ctx* out) {
@@ -560,6 +584,11 @@ itpp_status itpp_create(const itpp_config* cfg, itpp_ctx* out) {
 itpp_status itpp_destroy(itpp_ctx ctx) {
   if (!ctx) return ITPP_OK;
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->gate_stream) (void)hipStreamSynchronize(ctx->gate_stream);
+  drop_step_graph(ctx);
+  if (ctx->gate_stream) (void)hipStreamDestroy(ctx->gate_stream);
+  if (ctx->join_in) (void)hipEventDestroy(ctx->join_in);
+  if (ctx->join_out) (void)hipEventDestroy(ctx->join_out);
   free_ckpts(ctx);
   free_all(ctx);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
@@ -611,6 +640,7 @@ itpp_status itpp_set_hamiltonian(itpp_ctx c, int32_t n_terms, const uint64_t* x,
   c->sched_mult.clear();
   c->glist.clear();
   c->ready = false;
+  drop_step_graph(c);
   return ITPP_OK;
 }
 
@@ -631,6 +661,7 @@ itpp_status itpp_set_schedule(itpp_ctx c, int32_t n_gates, const int32_t* term_i
   c->sched_term.swap(st);
   c->sched_mult.swap(sm);
   c->glist.swap(gl);
+  drop_step_graph(c);
   return do_reset(c);
 }
 
@@ -875,17 +906,12 @@ static itpp_status build_gate(itpp_ctx c, int i, const std::vector<int>& pos, do
   const uint32_t nph = phase_needed ? (uint32_t)(2 * t.nsup) : 0u;
   gp.lflags = (uint32_t)gp.ov | ((uint32_t)gp.ovf << 2) | ((uint32_t)gp.w2 << 4) | (nph << 6) | (phflip << 9);
   gp.tile = gate_tile(c->NW, shape);
-  if (c->epoch % kStatusClearEvery == 0) HIP_TRY(c, launch_clear_status(c->status, c->status_cap, c->stream));
-  gp.epoch = c->epoch;
-  c->epoch = (c->epoch + 1) & 0x3fffffffu;
-  if (c->epoch == 0) c->epoch = 1;
   gp.delta = c->cfg.threshold;
   gp.cap_elems = c->cap;
   gp.status_cap = c->status_cap;
   gp.spec = spec ? 1 : 0;
   gp.spos = i < kRatioSlots ? i : -1;
   gp.spec_mult = c->spec_mult;
-  gp.serial = c->serial++;
   for (int b = 0; b < nbits; ++b) gp.pos_in[b] = (uint8_t)pos[b];
   std::memset(&rp, 0, sizeof(rp));
   rp.nbits = nbits;
@@ -904,7 +930,7 @@ static itpp_status enqueue_gate(itpp_ctx c, double dtau, bool spec) {
   if (bs != ITPP_OK) return bs;
   const int in = c->cur, out = c->cur ^ 1;
   const int pin = c->par, pout = c->par ^ 1;
-  HIP_TRY(c, launch_partition(c->NW, gp, c->side[in], c->plan + pin, c->ctl, c->part, c->stream));
+  HIP_TRY(c, launch_partition(c->NW, gp, c->side[in], c->plan + pin, c->ctl, c->part, c->status, c->stream));
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
   if (c->timing) {
     if (c->ev_used + 3 > 3 * 4096) HIP_TRY(c, drain_events(c));
@@ -924,25 +950,96 @@ static itpp_status enqueue_gate(itpp_ctx c, double dtau, bool spec) {
   if (c->timing) HIP_TRY(c, hipEventRecord(e1, c->stream));
   HIP_TRY(c, launch_select(c->NW, c->f32, c->side[out], c->plan + pout, c->filt + pin, c->filt + pout, c->plan + pin,
                            c->ctl, c->sel, rp, c->cfg.max_terms, c->cfg.cap_policy == ITPP_CAP_FAIL ? 1 : 0,
-                           gp.spec, gp.spos, gp.serial, c->cus * 4, c->stream));
+                           gp.spec, gp.spos, c->cus * 4, c->stream));
   if (c->timing) HIP_TRY(c, hipEventRecord(e2, c->stream));
   c->pos.swap(pos1);
   c->cur = out;
   c->par = pout;
   c->gpos = (i + 1) % G;
+  c->serial += 1;
   return ITPP_OK;
 }
 
-namespace {
-struct HostSnap {
-  std::vector<int> pos;
-  int cur, par, gpos;
-  uint64_t serial;
-  size_t ev_used;
-};
-}  // namespace
+static void drop_step_graph(itpp_ctx c) {
+  if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
+  c->step_exec = nullptr;
+  c->step_pos.clear();
+  c->step_snaps.clear();
+  c->step_cur = c->step_par = -1;
+}
+
+// Trotter steps in one recorded graph: a step of an odd number of gates
+// ends in the other ping-pong slots, two of them in the slots they started.
+static int graph_period(int G) { return G % 2 ? 2 : 1; }
+
+// Record the launches of graph_period Trotter steps starting at the current
+// host state (gpos == 0) as a graph.  Sets *ok = false (nothing recorded)
+// if they do not end in the bit order and slots they start from, so that
+// the graph could not be replayed.  The host state is unchanged.
+static itpp_status record_step(itpp_ctx c, double dtau, bool* ok) {
+  *ok = false;
+  const int G = (int)c->glist.size() * graph_period((int)c->glist.size());
+  const std::vector<int> pos0 = c->pos;
+  const int cur0 = c->cur, par0 = c->par;
+  const uint64_t serial0 = c->serial;
+  std::vector<HostSnap> snaps;
+  HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  itpp_status s = ITPP_OK;
+  for (int j = 0; j < G && s == ITPP_OK; ++j) {
+    snaps.push_back(HostSnap{c->pos, c->cur, c->par, c->gpos, c->serial - serial0, 0});
+    s = enqueue_gate(c, dtau, true);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(c->stream, &g);
+  const bool periodic = c->pos == pos0 && c->cur == cur0 && c->par == par0 && c->gpos == 0;
+  if (s != ITPP_OK || ee != hipSuccess || !periodic) {
+    if (g) (void)hipGraphDestroy(g);
+    c->pos = pos0;
+    c->cur = cur0;
+    c->par = par0;
+    c->gpos = 0;
+    c->serial = serial0;
+    if (s != ITPP_OK) return s;
+    if (ee != hipSuccess) return hip_fail(c, ee, "hipStreamEndCapture");
+    return ITPP_OK;
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  c->pos = pos0;
+  c->serial = serial0;
+  if (ie != hipSuccess) return hip_fail(c, ie, "hipGraphInstantiate");
+  drop_step_graph(c);
+  c->step_exec = ex;
+  c->step_pos = pos0;
+  c->step_cur = cur0;
+  c->step_par = par0;
+  c->step_dtau = dtau;
+  c->step_snaps = std::move(snaps);
+  *ok = true;
+  return ITPP_OK;
+}
+
+static itpp_status run_gates_on(itpp_ctx c, double dtau, int64_t n_gates, itpp_stats* st);
 
 static itpp_status run_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stats* st) {
+  if (c->stream != nullptr || !c->graphs || c->timing || c->ckpt_every > 0) return run_gates_on(c, dtau, n_gates, st);
+  if (!c->gate_stream) {
+    HIP_TRY(c, hipStreamCreateWithFlags(&c->gate_stream, hipStreamNonBlocking));
+    HIP_TRY(c, hipEventCreateWithFlags(&c->join_in, hipEventDisableTiming));
+    HIP_TRY(c, hipEventCreateWithFlags(&c->join_out, hipEventDisableTiming));
+  }
+  HIP_TRY(c, hipEventRecord(c->join_in, nullptr));
+  HIP_TRY(c, hipStreamWaitEvent(c->gate_stream, c->join_in, 0));
+  c->stream = c->gate_stream;
+  const itpp_status s = run_gates_on(c, dtau, n_gates, st);
+  c->stream = nullptr;
+  HIP_TRY(c, hipEventRecord(c->join_out, c->gate_stream));
+  HIP_TRY(c, hipStreamWaitEvent(nullptr, c->join_out, 0));
+  return s;
+}
+
+static itpp_status run_gates_on(itpp_ctx c, double dtau, int64_t n_gates, itpp_stats* st) {
   if (!c->ready) {
     itpp_status s = do_reset(c);
     if (s != ITPP_OK) return s;
@@ -963,6 +1060,7 @@ static itpp_status run_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stat
   }
   const uint64_t g0 = h0.gates;
   const uint64_t sg0 = h0.spec_gates;
+  c->serial = h0.gate_serial;
   const int G = (int)c->glist.size();
   int64_t retries = 0;
   int64_t done = 0;
@@ -985,8 +1083,13 @@ static itpp_status run_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stat
   // a speculative gate asked to be redone (all kernels after it were no-ops,
   // so that gate's input is intact) and replays from there without
   // speculation for that gate.
+  const bool can_graph = c->graphs && E == 0 && !c->timing && c->stream != nullptr && c->speculate && G > 0;
+  const int GR = G * graph_period(G);  // gates in one recorded graph
+  const int64_t g_steps0 = c->graph_steps;
   while (done < n_gates && G > 0) {
-    int64_t batch = std::min<int64_t>(n_gates - done, kSyncEvery);
+    // with step graphs, batches end on step boundaries
+    const int64_t span = can_graph ? (G - c->gpos) % G + std::max<int64_t>(1, kSyncEvery / GR) * GR : kSyncEvery;
+    int64_t batch = std::min<int64_t>(n_gates - done, span);
     if (E > 0 && c->fwd_valid) {
       // forward checkpoint of the state before gate fwd_gates, every E gates
       if (c->fwd_gates % E == 0 && (int64_t)c->ckpts.size() == c->fwd_gates / E) {
@@ -1006,13 +1109,41 @@ static itpp_status run_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stat
       batch = std::min<int64_t>(batch, E - c->fwd_gates % E);
     }
     snaps.clear();
-    for (int64_t b = 0; b < batch; ++b) {
+    // whole Trotter steps run as replays of a recorded graph when they can
+    // (no checkpoints or event timing, a stream that can be captured and a
+    // speculative first gate)
+    for (int64_t b = 0; b < batch;) {
+      if (c->gpos == 0 && can_graph && !(b == 0 && nospec_next) && batch - b >= GR) {
+        bool have = c->step_exec && c->step_pos == c->pos && c->step_cur == c->cur && c->step_par == c->par &&
+                    c->step_dtau == dtau;
+        // record once the step-start bit order repeats (from the second step)
+        if (!have && c->last_step_pos == c->pos) {
+          itpp_status s = record_step(c, dtau, &have);
+          if (s != ITPP_OK) return s;
+        }
+        c->last_step_pos = c->pos;
+        if (have) {
+          for (int j = 0; j < GR; ++j) {
+            HostSnap sn = c->step_snaps[j];
+            sn.serial += c->serial;
+            snaps.push_back(std::move(sn));
+          }
+          HIP_TRY(c, hipGraphLaunch(c->step_exec, c->stream));
+          c->serial += (uint64_t)GR;
+          c->graph_steps += graph_period(G);
+          b += GR;
+          continue;
+        }
+      } else if (c->gpos == 0) {
+        c->last_step_pos = c->pos;
+      }
       snaps.push_back(HostSnap{c->pos, c->cur, c->par, c->gpos, c->serial, c->ev_used});
       // with checkpoints the forward writes exactly what a recomputation
       // writes (no speculation), so stored states pack to the same layout
       const bool spec = c->speculate && E == 0 && !(b == 0 && nospec_next);
       itpp_status s = enqueue_gate(c, dtau, spec);
       if (s != ITPP_OK) return s;
+      ++b;
     }
     nospec_next = false;
     Ctl h{};
@@ -1027,6 +1158,7 @@ static itpp_status run_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stat
       c->cur = sn.cur;
       c->par = sn.par;
       c->gpos = sn.gpos;
+      c->serial = h.halt_serial + 1;  // the redone gate's serial on the device
       // keep the timing of the failed attempt, drop the no-op launches after it
       if (c->timing) c->ev_used = std::min(c->ev_used, sn.ev_used + 3);
       HIP_TRY(c, launch_prepare(c->plan + (c->par ^ 1), c->ctl, c->stream));
@@ -1058,6 +1190,7 @@ static itpp_status run_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stat
     st->c_I_min = h.cI_min;
     st->c_I_max = h.cI_max;
     st->kth_abs_min = h.kth_min;
+    st->graph_steps = c->graph_steps - g_steps0;
   }
   if (c->timing) {
     Ctl h{};
@@ -1070,6 +1203,8 @@ static itpp_status run_gates(itpp_ctx c, double dtau, int64_t n_gates, itpp_stat
 
 itpp_status itpp_set_option(itpp_ctx c, int32_t option, double value) {
   if (!c) return ITPP_ERR_ARG;
+  // a recorded step holds the launch arguments of the old settings
+  drop_step_graph(c);
   switch (option) {
     case ITPP_OPT_SPECULATION:
       if (value != 0.0 && value != 1.0) return fail(c, ITPP_ERR_ARG, "speculation must be 0 or 1");
@@ -1091,6 +1226,10 @@ itpp_status itpp_set_option(itpp_ctx c, int32_t option, double value) {
         c->fwd_valid = false;
         free_ckpts(c);
       }
+      return ITPP_OK;
+    case ITPP_OPT_GRAPHS:
+      if (value != 0.0 && value != 1.0) return fail(c, ITPP_ERR_ARG, "graphs must be 0 or 1");
+      c->graphs = value != 0.0;
       return ITPP_OK;
     default:
       return fail(c, ITPP_ERR_ARG, "unknown option");
@@ -1477,7 +1616,7 @@ itpp_status adjoint_gate(itpp_ctx c, int64_t g, const Snapshot& Sin, const Snaps
   RepPos rp;
   itpp_status bs = build_gate(c, i, Sin.pos, c->fwd_dtau, false, 0, gp, pos1, rp);
   if (bs != ITPP_OK) return bs;
-  HIP_TRY(c, launch_partition(c->NW, gp, Sin.side, Sin.plan, c->ctl, c->part, c->stream));
+  HIP_TRY(c, launch_partition(c->NW, gp, Sin.side, Sin.plan, c->ctl, c->part, c->status, c->stream));
   AdjArgs a{};
   a.lam_out = B.lam[cur];
   a.lam_in = B.lam[cur ^ 1];
@@ -1848,6 +1987,7 @@ itpp_status itpp_batch_autotune(itpp_batch b, const double* dtau, int64_t warm_g
     for (int w : wk) {
       for (itpp_ctx c : b->inst) {
         c->shape = c->NW == 4 ? (sh >> 1) & 1 : sh & 1;
+        drop_step_graph(c);
         itpp_status s = itpp_reset(c);
         if (s != ITPP_OK) return batch_fail(b, s, c->err);
       }
@@ -1874,6 +2014,7 @@ itpp_status itpp_batch_autotune(itpp_batch b, const double* dtau, int64_t warm_g
   }
   for (itpp_ctx c : b->inst) {
     c->shape = c->NW == 4 ? (bs >> 1) & 1 : bs & 1;
+    drop_step_graph(c);
     itpp_status s = itpp_reset(c);
     if (s != ITPP_OK) return batch_fail(b, s, c->err);
   }

@@ -39,11 +39,20 @@ namespace itpp {
 // split by the boundary is moved into the earlier tile.
 template <int NW>
 __global__ __launch_bounds__(256) void partition_kernel(GateParams gp, Side in, const Plan* __restrict__ plan_in,
-                                                         uint64_t* __restrict__ part, Ctl* __restrict__ ctl) {
+                                                         uint64_t* __restrict__ part, Ctl* __restrict__ ctl,
+                                                         TileStatus* __restrict__ status) {
   __shared__ JoinLayout L;
   if (threadIdx.x == 0) make_layout(L, plan_in, gp.w, gp.tile);
   __syncthreads();
   if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kErrNone || ctl->halt) return;
+  // the look-back records carry 12-bit epoch tags that repeat every 4095
+  // gates: clear them all every kStatusClearEvery gates (before the gate
+  // kernel of this gate reads them; nothing else runs in between)
+  if (ctl->epoch % kStatusClearEvery == 0) {
+    const uint64_t nwords = (uint64_t)kStatusWords * gp.status_cap;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += stride) status[i] = 0ull;
+  }
   const int lane = threadIdx.x & 63;
   const int grp = lane >> 3, sl = lane & 7;
   const uint64_t b = ((uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * 8 + (uint64_t)grp;
@@ -338,6 +347,7 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
   // nothing at all (not even the plan prologue) after an error or a halt
   if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kErrNone || ctl->halt) return;
   const Filter fin = *filt_in;
+  const uint32_t epoch = ctl->epoch;
   const T ch = (T)gp.ch, sh = (T)gp.sh;
   const int nbits = gp.nbits;
   const int w = gp.w;
@@ -568,8 +578,8 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
       }
       constexpr int NQ = 2 * kMaxClasses;
       const uint64_t SN = gp.status_cap;
-      const unsigned long long tag32 = (unsigned long long)gp.epoch << 32;
-      const unsigned long long tag12 = (unsigned long long)(gp.epoch % 4095u + 1u) << 52;
+      const unsigned long long tag32 = (unsigned long long)epoch << 32;
+      const unsigned long long tag12 = (unsigned long long)(epoch % 4095u + 1u) << 52;
       const unsigned long long kInclReady = 1ull << 48;
       unsigned long long aw[2];
 #pragma unroll
@@ -684,7 +694,7 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
                 for (;;) {
                   const unsigned long long x =
                       __hip_atomic_load(&status[(2 + lane) * SN + kp], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                  if ((x >> 32) == gp.epoch) {
+                  if ((x >> 32) == epoch) {
                     iv = (uint32_t)x;
                     break;
                   }
@@ -898,14 +908,14 @@ int gate_min_tile(int nw) { return std::min(std::min(gate_tile(nw, 0), gate_tile
 int gate_wgs_per_cu(int shape) { return shape == 1 ? GateShape<1>::wgs_per_cu : GateShape<0>::wgs_per_cu; }
 
 hipError_t launch_partition(int nw, const GateParams& gp, Side in, const Plan* plan_in, Ctl* ctl, uint64_t* part,
-                            hipStream_t st) {
+                            TileStatus* status, hipStream_t st) {
   // eight tile boundaries per wavefront, four wavefronts per block
   const uint64_t nb = gp.status_cap + kMaxClasses;
   const int pgrid = (int)((nb + 31) / 32);
   if (nw == 2)
-    hipLaunchKernelGGL(partition_kernel<2>, dim3(pgrid), dim3(256), 0, st, gp, in, plan_in, part, ctl);
+    hipLaunchKernelGGL(partition_kernel<2>, dim3(pgrid), dim3(256), 0, st, gp, in, plan_in, part, ctl, status);
   else
-    hipLaunchKernelGGL(partition_kernel<4>, dim3(pgrid), dim3(256), 0, st, gp, in, plan_in, part, ctl);
+    hipLaunchKernelGGL(partition_kernel<4>, dim3(pgrid), dim3(256), 0, st, gp, in, plan_in, part, ctl, status);
   return hipGetLastError();
 }
 

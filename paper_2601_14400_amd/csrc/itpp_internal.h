@@ -33,6 +33,7 @@ constexpr int kFineBins = 1024;              // fine |c| histogram around the pr
 constexpr int kFineShift = 38;               // bin width 2^38 ulps of the f64 pattern
 constexpr uint64_t kFineHalf = 1ull << 47;   // window half width (~2.2% relative)
 constexpr int kRatioSlots = 1024;            // schedule positions with a recorded K-th value ratio
+constexpr uint32_t kStatusClearEvery = 2048; // look-back tags are 12-bit epochs (4095 values)
 
 // Description of a stored state (written by the gate that produced it).
 struct Plan {
@@ -57,10 +58,23 @@ struct Filter {
   uint64_t ref_bits;         // |c| bits near which the next gate's K-th value is expected (0: none)
 };
 
+// The epoch after e (skips 0; the wrap lands on a multiple of
+// kStatusClearEvery, so the records are cleared before the next use).
+__host__ __device__ inline uint32_t next_epoch(uint32_t e) { return e + 1u == 0u ? kStatusClearEvery : e + 1u; }
+
 // Per-run control block (device).
 struct Ctl {
   uint32_t ticket;           // tile ticket of the running gate
   uint32_t error;            // sticky error code (see kErr*)
+  // Look-back tag of the running gate and its serial number: advanced on the
+  // device once per gate attempt (select_decide, adj_reduce_kernel), so the
+  // launches of a gate carry no per-launch arguments and a recorded graph
+  // of a Trotter step can be replayed.  The look-back records are cleared
+  // whenever the epoch is a multiple of kStatusClearEvery (partition_kernel);
+  // it starts at kStatusClearEvery and is never 0, the tag of a cleared record.
+  uint32_t epoch;
+  uint32_t pad_epoch;
+  uint64_t gate_serial;
   uint64_t n_written_nonid;  // written non-identity outputs of the running gate
   double cI_out;             // identity output of the running gate
   uint32_t have_cI;
@@ -148,9 +162,7 @@ struct GateParams {
   int32_t spos;              // schedule position (index of kth_ratio), -1: none
   uint64_t qm1[kMaxKeyWords];    // this gate's flip mask in the next rep (branch key = self key ^ qm1)
   double spec_mult;          // that margin as a factor of the predicted value
-  uint64_t serial;           // host serial number of this gate launch
   int32_t tile;              // merged elements per tile
-  uint32_t epoch;            // unique per launched gate (look-back tags)
   uint32_t check_write_threshold;
   double delta;              // keep |c| > delta
   uint64_t cap_elems;        // capacity of each side in elements
@@ -190,7 +202,7 @@ struct SelBuf {
 // itpp_kernels.hip).
 hipError_t launch_init(int nw, int f32, Side s0, Plan* plan, Filter* filt, Ctl* ctl, int w0, hipStream_t st);
 hipError_t launch_partition(int nw, const GateParams& gp, Side in, const Plan* plan_in, Ctl* ctl, uint64_t* part,
-                            hipStream_t st);
+                            TileStatus* status, hipStream_t st);
 hipError_t launch_gate(int nw, int f32, int shape, const GateParams& gp, Side in, Side out, const Plan* plan_in,
                        Plan* plan_out, const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part,
                        int grid, hipStream_t st);
@@ -200,7 +212,7 @@ hipError_t launch_gate_rt(int nw, int f32, int shape, const GateParams& gp, Side
                        int grid, hipStream_t st);
 hipError_t launch_select(int nw, int f32, Side out, const Plan* plan_out, const Filter* filt_in,
                          Filter* filt_out, Plan* plan_next, Ctl* ctl, SelBuf sel, const RepPos& rp,
-                         int64_t K, int cap_fail, int spec, int spos, uint64_t serial, int grid, hipStream_t st);
+                         int64_t K, int cap_fail, int spec, int spos, int grid, hipStream_t st);
 hipError_t launch_prepare(Plan* plan_out, Ctl* ctl, hipStream_t st);
 hipError_t launch_adjoint_gate(int nw, const GateParams& gp, Side in, const Plan* plan_in, Plan* plan_scratch,
                                const Filter* filt_in, Ctl* ctl, TileStatus* status, uint64_t* part,
@@ -211,7 +223,6 @@ hipError_t launch_pack(int nw, int f32, Side src, const Plan* plan_src, Side dst
                        hipStream_t st);
 hipError_t launch_seed(int nw, Side s, const Plan* plan, const Filter* filt, const RepPos& rp, const uint64_t* ox,
                        const uint64_t* oz, const double* oc, int32_t m, double* lam, hipStream_t st);
-hipError_t launch_clear_status(TileStatus* status, uint64_t n, hipStream_t st);
 hipError_t launch_observe(int nw, int f32, Side s, const Plan* plan, const Filter* filt, const RepPos& rp,
                           const uint64_t* ox, const uint64_t* oz, const double* oc, int32_t m,
                           double* result, Ctl* ctl, hipStream_t st);

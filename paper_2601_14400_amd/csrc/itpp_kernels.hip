@@ -31,6 +31,7 @@ __global__ void init_kernel(Side s0, Plan* plan, Filter* filt, Ctl* ctl, int w0)
   f.n_survivors = 1;
   *filt = f;
   Ctl c = {};
+  c.epoch = kStatusClearEvery;  // the first gate clears the look-back records
   *ctl = c;
 }
 
@@ -80,8 +81,7 @@ __device__ inline void find_from_top(const uint32_t* h, int nbins, uint64_t base
 // binds and which bit range of |c| holds the (K-1)-th largest non-identity
 // value; prepare the control block for the next gate.
 __global__ __launch_bounds__(1024) void select_decide(const Filter* filt_in, Filter* filt_out, Plan* plan_next,
-                                                      Ctl* ctl, int64_t K, int cap_fail, int spec, int spos,
-                                                      uint64_t serial) {
+                                                      Ctl* ctl, int64_t K, int cap_fail, int spec, int spos) {
   __shared__ uint32_t fh[kFineBins];
   __shared__ uint64_t scr[1024];
   __shared__ int s_bin;
@@ -97,7 +97,10 @@ __global__ __launch_bounds__(1024) void select_decide(const Filter* filt_in, Fil
       __syncthreads();
       if (tid == 0) {
         ctl->halt = 1u;
-        ctl->halt_serial = serial;
+        ctl->halt_serial = ctl->gate_serial;
+        // the redone gate is a new attempt with a fresh look-back tag
+        ctl->gate_serial += 1;
+        ctl->epoch = next_epoch(ctl->epoch);
       }
       return;
     }
@@ -188,19 +191,9 @@ __global__ __launch_bounds__(1024) void select_decide(const Filter* filt_in, Fil
     ctl->n_written_nonid = 0;
     ctl->n_above_hi = 0;
     ctl->have_cI = 0;
+    ctl->gate_serial += 1;
+    ctl->epoch = next_epoch(ctl->epoch);
   }
-}
-
-// Reset the look-back records (their 12-bit epoch tags repeat every 4095
-// gates; the host clears them more often than that).
-__global__ void clear_status_kernel(TileStatus* status, uint64_t n) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * n; i += stride) status[i] = 0;
-}
-
-hipError_t launch_clear_status(TileStatus* status, uint64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(clear_status_kernel, dim3(256), dim3(256), 0, st, status, n);
-  return hipGetLastError();
 }
 
 // Clear what a gate accumulates, before a gate is redone after a failed
@@ -844,6 +837,7 @@ __global__ __launch_bounds__(256) void adj_reduce_kernel(const double* part, con
     *dtheta_out = __dadd_rn(r[0][0], r[1][0]);
     *s_out = __dadd_rn(r[2][0], r[3][0]);
     ctl->ticket = 0;
+    ctl->epoch = next_epoch(ctl->epoch);  // the reverse gate's look-back used this tag
   }
 }
 
@@ -887,9 +881,9 @@ hipError_t launch_prepare(Plan* plan_out, Ctl* ctl, hipStream_t st) {
 
 hipError_t launch_select(int nw, int f32, Side out, const Plan* plan_out, const Filter* filt_in,
                          Filter* filt_out, Plan* plan_next, Ctl* ctl, SelBuf sel, const RepPos& rp,
-                         int64_t K, int cap_fail, int spec, int spos, uint64_t serial, int grid, hipStream_t st) {
+                         int64_t K, int cap_fail, int spec, int spos, int grid, hipStream_t st) {
   hipLaunchKernelGGL(select_decide, dim3(1), dim3(1024), 0, st, filt_in, filt_out, plan_next, ctl, K,
-                     cap_fail, spec, spos, serial);
+                     cap_fail, spec, spos);
   ITPP_DISPATCH(nw, f32, {
     hipLaunchKernelGGL((select_coarse_hist<NWC, TC>), dim3(grid / 4 > 0 ? grid / 4 : 1), dim3(256), 0, st, out,
                        plan_out, ctl);

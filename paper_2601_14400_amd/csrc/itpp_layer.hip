@@ -331,6 +331,7 @@ void layer_kernel(GateParams gp, Side in, Side out, const Plan* __restrict__ pla
   const int tid = threadIdx.x;
   if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kErrNone || ctl->halt) return;
   const double cI = filt_in->cI;
+  const uint32_t epoch = ctl->epoch;
   const uint64_t kth_bits = filt_in->kth_bits;
   const bool cap_active = filt_in->cap_active != 0;
   const bool tie_active = filt_in->tie_active != 0;
@@ -614,7 +615,7 @@ void layer_kernel(GateParams gp, Side in, Side out, const Plan* __restrict__ pla
     // (4) look-back across the tiles of this join (wave 0)
     if (tid < 64) {
       uint32_t excl[2 * kMaxClasses];
-      layer_lookback(status, gp.status_cap, t, t == first, (int64_t)first, gp.epoch, sm.tot0, sm.tot1, ctl, excl);
+      layer_lookback(status, gp.status_cap, t, t == first, (int64_t)first, epoch, sm.tot0, sm.tot1, ctl, excl);
       if (tid == 0) {
 #pragma unroll
         for (int q = 0; q < 2 * kMaxClasses; ++q) sm.excl[q] = excl[q];
