@@ -130,7 +130,8 @@ def parse():
     ap.add_argument("--beta", type=float, default=2.0, help="final inverse temperature (default 2)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form", choices=["fp64", "fp32", "batched", "adjoint", "squared", "realtime"], default="fp64")
+    ap.add_argument("--form", choices=["fp64", "fp32", "batched", "adjoint", "squared", "realtime", "small"],
+                    default="fp64")
     ap.add_argument("--progress", action="store_true", help="print a line after every tenth of the Trotter steps")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="end with three 256 MiB device copies (the byte counters' calibration in a --pmc run)")
@@ -234,6 +235,63 @@ def run_form_fp32(args):
                     "fp64_roofline_frac": out["f64"]["roofline"]["frac"],
                     "observables_fp32": vals["f32"], "observables_fp64": vals["f64"],
                     "abs_error_vs_fp64": {k: abs(vals["f32"][k] - vals["f64"][k]) for k in vals["f32"]}}
+    return line, w
+
+
+def run_form_small(args):
+    """The 8-qubit untruncated workload (12,870 strings, 16 gates a step,
+    320 gates a run): kernels of a few microseconds, so the wall time is set
+    by launches and host synchronisation.  Whole runs (reset + 20 steps) are
+    timed with step graphs (the default) and with one launch per kernel; a
+    separate event-timed run gives the kernels' own time."""
+    import torch
+
+    import itpp_workloads as W
+    import paper_2601_14400_amd as P
+
+    w = W.config1()
+    reps = 100 * args.steps
+    res = {}
+    for mode in ("graphs", "direct"):
+        eng = P.engine_for(w)
+        eng.set_option("graphs", 1 if mode == "graphs" else 0)
+        for _ in range(max(1, args.warmup) * 5):
+            eng.reset()
+            eng.evolve(w.dtau, w.n_steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tu = 0.0
+        gsteps = 0
+        for _ in range(reps):
+            eng.reset()
+            st = eng.evolve(w.dtau, w.n_steps)
+            tu += st["term_updates"]
+            gsteps += st["graph_steps"]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[mode] = {"value": tu / dt, "ms_per_run": dt * 1e3 / reps, "us_per_gate": dt * 1e6 / reps / st["n_gates"],
+                     "graph_steps_per_run": gsteps / reps, "terms": st["n_terms"]}
+        if mode == "graphs":
+            vals = {k: eng.expect(a, b) for k, (a, b) in w.observables.items()}
+        eng.close()
+        progress(f"{mode}: {res[mode]['ms_per_run']:.3f} ms per run")
+    eng = P.engine_for(w)
+    eng.set_timing(True)
+    eng.reset()
+    st = eng.evolve(w.dtau, w.n_steps)
+    tim = eng.timing()
+    eng.close()
+    kern_us = (tim["gate_ms"] + tim["select_ms"]) * 1e3 / max(1, tim["gate_launches"])
+    line = base_line(args, res["graphs"]["value"], res["graphs"]["ms_per_run"], "f64",
+                     {"workload": f"tfim_n{w.n}_periodic_first_order_dtau{w.dtau}_beta{w.n_steps * w.dtau:g}"
+                                  f"_delta{w.delta:g}_untruncated", "form": "small", "n_qubits": w.n,
+                      "trotter_steps": w.n_steps, "gates_per_run": st["n_gates"], "runs_timed": reps})
+    line["roofline"] = roofline_of(tim)
+    line["form"] = {"launch_bound": True, "graphs": res["graphs"], "direct": res["direct"],
+                    "graphs_over_direct": res["graphs"]["value"] / res["direct"]["value"],
+                    "kernel_us_per_gate": kern_us,
+                    "kernel_share_of_wall_graphs": kern_us / res["graphs"]["us_per_gate"],
+                    "observables": vals}
     return line, w
 
 
@@ -498,7 +556,8 @@ def main():
     if args.form != "fp64":
         torch.cuda.set_device(0)
         line, w = {"fp32": run_form_fp32, "batched": run_form_batched, "adjoint": run_form_adjoint,
-                   "squared": run_form_squared, "realtime": run_form_realtime}[args.form](args)
+                   "squared": run_form_squared, "realtime": run_form_realtime,
+                   "small": run_form_small}[args.form](args)
         if not args.no_cpu_baseline:
             progress("cpu baseline")
             base = {"squared": cpu_baseline_squared, "realtime": cpu_baseline_realtime}.get(args.form, cpu_baseline)

@@ -426,6 +426,18 @@ struct JoinLayout {
   int njoin, full;
 };
 
+// Copy of a Plan in LDS made with one 4-byte load per thread (threads t in
+// [0, sizeof(Plan)/4) take part; callers pass their thread index minus an
+// offset to use other threads, and synchronise before reading).  The
+// prologue arithmetic on a plan (class views, join layout, region bases) is
+// a chain of dependent reads: from global memory, where the previous kernel
+// left the plan, each would be a round trip of a microsecond or more.
+__device__ __forceinline__ void plan_to_lds(Plan* dst, const Plan* __restrict__ src, int t) {
+  static_assert(sizeof(Plan) % 4 == 0, "the plan is copied in 4-byte words");
+  constexpr int kWords = (int)(sizeof(Plan) / 4);
+  if (t >= 0 && t < kWords) reinterpret_cast<uint32_t*>(dst)[t] = reinterpret_cast<const uint32_t*>(src)[t];
+}
+
 __device__ inline void make_layout(JoinLayout& L, const Plan* __restrict__ pin, int w, int tile) {
   const int ncls = 1 << w;
   L.full = ncls - 1;

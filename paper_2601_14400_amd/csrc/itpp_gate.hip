@@ -42,7 +42,10 @@ __global__ __launch_bounds__(256) void partition_kernel(GateParams gp, Side in, 
                                                          uint64_t* __restrict__ part, Ctl* __restrict__ ctl,
                                                          TileStatus* __restrict__ status) {
   __shared__ JoinLayout L;
-  if (threadIdx.x == 0) make_layout(L, plan_in, gp.w, gp.tile);
+  __shared__ Plan s_pin;
+  plan_to_lds(&s_pin, plan_in, threadIdx.x);
+  __syncthreads();
+  if (threadIdx.x == 0) make_layout(L, &s_pin, gp.w, gp.tile);
   __syncthreads();
   if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kErrNone || ctl->halt) return;
   // the look-back records carry 12-bit epoch tags that repeat every 4095
@@ -362,12 +365,16 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
 
   for (int i = tid; i < kFineBins; i += BLOCK) sm.fhist[i] = 0;
   if (tid < kMaxClasses * kMaxClasses) sm.ncnt[tid] = 0;
+  __shared__ Plan s_pin, s_pn;
+  plan_to_lds(&s_pin, plan_in, tid);
+  if constexpr (ADJ) plan_to_lds(&s_pn, adj.plan_next, tid - 128);
+  __syncthreads();
   if (tid == 0) {
-    const Plan* __restrict__ pin = plan_in;
+    const Plan* __restrict__ pin = &s_pin;
     uint64_t acc = 0;
     if constexpr (ADJ) {
       // the forward output, packed: region (c, e) holds exactly cnt[c][e]
-      const Plan* __restrict__ pn = adj.plan_next;
+      const Plan* __restrict__ pn = &s_pn;
       for (int c = 0; c < kMaxClasses; ++c)
         for (int e = 0; e < kMaxClasses; ++e) {
           sm.out_base[c][e] = acc;
@@ -401,6 +408,11 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
     if (blockIdx.x == 0 && tid == 0) *adj.ntiles = total_tiles;
   }
   if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kErrNone || ctl->halt) return;
+  // tickets go out in arrival order, so the first total_tiles workgroups
+  // can take them all: the others leave without touching the ticket counter
+  // (for small states, hundreds of idle workgroups would otherwise queue on
+  // that one atomic)
+  if ((uint64_t)blockIdx.x >= total_tiles) return;
   if (tid == 0) {
     uint32_t t0;
     uint64_t pf[4];

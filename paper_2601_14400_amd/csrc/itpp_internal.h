@@ -15,6 +15,7 @@
 // produced it, e = class under the gate that will read it.  The reader sees
 // its class e as the concatenation over c of regions (c, e), which is sorted.
 #pragma once
+#include <cstddef>
 #include <cstdint>
 
 #include <hip/hip_runtime.h>
@@ -64,8 +65,14 @@ __host__ __device__ inline uint32_t next_epoch(uint32_t e) { return e + 1u == 0u
 
 // Per-run control block (device).
 struct Ctl {
-  uint32_t ticket;           // tile ticket of the running gate
+  // The tile ticket of the running gate, alone in its 128-byte line: every
+  // tile takes one with a device-scope atomic, and other traffic to the same
+  // line would queue behind those atomics.
+  uint32_t ticket;
+  uint32_t pad_ticket[31];
+  // Read by every workgroup when it starts (one line).
   uint32_t error;            // sticky error code (see kErr*)
+  uint32_t halt;             // 1: a speculative gate must be redone; later kernels do nothing
   // Look-back tag of the running gate and its serial number: advanced on the
   // device once per gate attempt (select_decide, adj_reduce_kernel), so the
   // launches of a gate carry no per-launch arguments and a recorded graph
@@ -75,12 +82,16 @@ struct Ctl {
   uint32_t epoch;
   uint32_t pad_epoch;
   uint64_t gate_serial;
+  uint64_t halt_serial;      // serial of the gate that asked to be redone
+  uint32_t pad_read[24];
+  // Added to by workgroups when they finish.
   uint64_t n_written_nonid;  // written non-identity outputs of the running gate
+  uint64_t n_above_hi;       // written non-identity outputs above the fine window
   double cI_out;             // identity output of the running gate
   uint32_t have_cI;
+  uint32_t pad_cnt[25];
   uint32_t hist[kHistBins];
   uint32_t fhist[kFineBins];
-  uint64_t n_above_hi;       // written non-identity outputs above the fine window
   // selection scratch
   uint64_t sel_lo, sel_hi;   // |c| bit range that holds the K-th value
   uint32_t sel_need;         // elements still needed from that range
@@ -93,8 +104,6 @@ struct Ctl {
   double alg_elems;          // sum over gates of survivors in + survivors out
   uint64_t gates;
   uint32_t cap_hit;
-  uint32_t halt;             // 1: a speculative gate must be redone; later kernels do nothing
-  uint64_t halt_serial;      // serial of that gate
   uint64_t spec_gates;       // gates that ran with a speculative write threshold
   double written_elems;      // sum over gates of the strings stored (identity included)
   // over the gates since the host last set them (run statistics):
@@ -104,6 +113,8 @@ struct Ctl {
   // value predicted from its input (the last time that position ran; 0: none)
   float kth_ratio[kRatioSlots];
 };
+static_assert(offsetof(Ctl, error) == 128 && offsetof(Ctl, n_written_nonid) == 256 && offsetof(Ctl, hist) == 384,
+              "the ticket, the start-of-workgroup reads and the end-of-workgroup counters have a line each");
 
 enum : uint32_t {
   kErrNone = 0,

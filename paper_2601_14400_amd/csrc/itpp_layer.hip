@@ -344,8 +344,11 @@ void layer_kernel(GateParams gp, Side in, Side out, const Plan* __restrict__ pla
   gate_window(*filt_in, gp, ctl, win_lo, win_hi, tw);
   for (int i = tid; i < kFineBins; i += BLOCK) sm.fhist[i] = 0;
   if (tid < kMaxClasses * kMaxClasses) sm.ncnt[tid] = 0;
+  __shared__ Plan s_pin;
+  plan_to_lds(&s_pin, plan_in, tid);
+  __syncthreads();
   if (tid == 0) {
-    const Plan* __restrict__ pin = plan_in;
+    const Plan* __restrict__ pin = &s_pin;
     const int ov = (int)(gp.lflags & 3u);
     // output region capacities: cap(c, e) = n[c][e] + n[~c][e ^ ov]
     uint64_t acc = 0;
@@ -369,6 +372,8 @@ void layer_kernel(GateParams gp, Side in, Side out, const Plan* __restrict__ pla
   __syncthreads();
   const uint64_t total_tiles = sm.L.tiles_before[sm.L.njoin];
   if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kErrNone || ctl->halt) return;
+  // the first total_tiles workgroups can take every ticket (arrival order)
+  if ((uint64_t)blockIdx.x >= total_tiles) return;
   if (tid == 0) {
     uint32_t t0, ct;
     uint64_t pf[4], ab, bb;
