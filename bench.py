@@ -318,8 +318,9 @@ def run_form_batched(args):
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     b = P.batch_for(ws)
-    shape, workers, rate = b.autotune(dts, 60, 60)
-    progress(f"autotune: shapes {shape} (bit 0: n <= 64, bit 1: n > 64) workers {workers} probe rate {rate:.3e}")
+    shape, workers, grid_div, rate = b.autotune(dts, 300, 150)
+    progress(f"autotune: shapes {shape % 3} (n <= 64) and {shape // 3} (n > 64), workers {workers}, "
+             f"grid divisor {grid_div}, probe rate {rate:.3e}")
     for _ in range(args.warmup):
         for e in b.instances:
             e.reset()
@@ -339,7 +340,7 @@ def run_form_batched(args):
     big = max(ws, key=lambda w: w.n * w.n_steps)
     progress(f"roofline run: n={big.n}, {big.n_steps} steps")
     e = P.engine_for(big)
-    e.set_option("gate_shape", (shape >> 1) & 1 if big.n > 64 else shape & 1)
+    e.set_option("gate_shape", shape // 3 if big.n > 64 else shape % 3)
     e.set_timing(True)
     e.evolve(big.dtau, big.n_steps)
     roof = roofline_of(e.timing())
@@ -349,8 +350,9 @@ def run_form_batched(args):
                       "instances": 64, "K": K, "gates": int(sum(2 * w.n * w.n_steps for w in ws))})
     line["roofline"] = roof
     line["form"] = {"sequential_value": tu_seq / t_seq, "sequential_s": t_seq, "batched_s": dt / args.steps,
-                    "batched_over_sequential": (tu / dt) / (tu_seq / t_seq), "autotune_shape": shape,
-                    "autotune_workers": workers}
+                    "batched_over_sequential": (tu / dt) / (tu_seq / t_seq),
+                    "autotune_shape_small": shape % 3, "autotune_shape_large": shape // 3,
+                    "autotune_workers": workers, "autotune_grid_div": grid_div}
     return line, big
 
 

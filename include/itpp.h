@@ -309,13 +309,19 @@ itpp_status itpp_num_gates(itpp_ctx ctx, int64_t* out);
  *    the null stream's earlier work and that the null stream then waits
  *    for, so the ordering seen by the caller is unchanged.  Results are
  *    bit-identical with and without graphs.  Changing an option, the
- *    Hamiltonian or the schedule drops the recorded graph. */
+ *    Hamiltonian or the schedule drops the recorded graph.
+ *  ITPP_OPT_GRID_DIV (default 1; 1, 2, 4 or 8): the gate kernel launches the
+ *    workgroups that fit on the device at once divided by this (its tiles
+ *    are taken from a ticket counter, so any grid covers every tile).
+ *    Smaller grids leave room for the kernels of other contexts running
+ *    concurrently (the batch); results do not depend on it. */
 typedef enum {
   ITPP_OPT_SPECULATION = 1,
   ITPP_OPT_SPEC_MARGIN = 2,
   ITPP_OPT_GATE_SHAPE = 3,
   ITPP_OPT_REAL_TIME = 4,
-  ITPP_OPT_GRAPHS = 5
+  ITPP_OPT_GRAPHS = 5,
+  ITPP_OPT_GRID_DIV = 6
 } itpp_option;
 itpp_status itpp_set_option(itpp_ctx ctx, int32_t option, double value);
 
@@ -351,15 +357,17 @@ itpp_status itpp_batch_set_workers(itpp_batch b, int32_t workers);
  * itpp_batch_last_error). */
 itpp_status itpp_batch_evolve(itpp_batch b, const double* dtau, const int64_t* n_steps, itpp_stats* st);
 
-/* Autotuner: for every choice of gate kernel shape (ITPP_OPT_GATE_SHAPE 0
- * or 1, chosen separately for instances with n <= 64 and n > 64) and 2, 4,
- * 8 workers, reset all instances, apply warm_gates gates untimed, then time
- * probe_gates more gates on every instance; keep the combination with the
- * most term updates per second (written to the non-NULL outputs; best_shape
- * bit 0 is the shape for n <= 64, bit 1 the shape for n > 64).  Leaves every
- * instance reset with the chosen shapes. */
+/* Autotuner, by coordinate descent: first the gate kernel shape
+ * (ITPP_OPT_GATE_SHAPE 0, 1 or 2, chosen separately for instances with
+ * n <= 64 and n > 64; nine pairs), then the worker count (2, 4, 8, 16),
+ * then the grid divisor (ITPP_OPT_GRID_DIV 1, 2, 4, 8).  Each probe resets
+ * all instances, applies warm_gates gates untimed, then times probe_gates
+ * more gates on every instance and scores term updates per second.  The
+ * best setting is written to the non-NULL outputs (best_shape = shape for
+ * n <= 64 + 3 * shape for n > 64) and left applied, every instance reset. */
 itpp_status itpp_batch_autotune(itpp_batch b, const double* dtau, int64_t warm_gates, int64_t probe_gates,
-                                int32_t* best_shape, int32_t* best_workers, double* best_rate);
+                                int32_t* best_shape, int32_t* best_workers, int32_t* best_grid_div,
+                                double* best_rate);
 
 /* Message for the last batch error (b == NULL: last creation failure). */
 const char* itpp_batch_last_error(itpp_batch b);

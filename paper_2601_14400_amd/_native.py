@@ -104,7 +104,7 @@ def load_library(path: Optional[str] = None):
     lib.itpp_batch_set_workers.argtypes = [vp, i32]
     lib.itpp_batch_evolve.argtypes = [vp, vp, vp, vp]
     lib.itpp_batch_autotune.argtypes = [vp, vp, i64, i64, ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                        ctypes.POINTER(dbl)]
+                                        ctypes.POINTER(i32), ctypes.POINTER(dbl)]
     lib.itpp_batch_last_error.argtypes = [vp]
     lib.itpp_batch_last_error.restype = ctypes.c_char_p
     lib.itpp_last_error.argtypes = [vp]
@@ -303,7 +303,8 @@ class Engine:
                 "graph_steps": st.graph_steps}
 
     def set_option(self, name: str, value: float):
-        opt = {"speculation": 1, "spec_margin": 2, "gate_shape": 3, "real_time": 4, "graphs": 5}[name]
+        opt = {"speculation": 1, "spec_margin": 2, "gate_shape": 3, "real_time": 4, "graphs": 5,
+               "grid_div": 6}[name]
         self._check(self._lib.itpp_set_option(self._h, opt, float(value)))
 
     def set_timing(self, enable: bool = True):
@@ -446,12 +447,15 @@ class Batch:
             out.append(Engine._stats(st[i]))
         return out
 
-    def autotune(self, dtaus: Sequence[float], warm_gates: int, probe_gates: int) -> Tuple[int, int, float]:
+    def autotune(self, dtaus: Sequence[float], warm_gates: int, probe_gates: int) -> Tuple[int, int, int, float]:
+        """(shape code = shape for n <= 64 + 3 * shape for n > 64, workers,
+        grid divisor, probe rate); the setting is left applied."""
         d = np.ascontiguousarray(dtaus, dtype=np.float64)
-        sh, wk, rate = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        sh, wk, gd, rate = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         self._check(self._lib.itpp_batch_autotune(self._h, d.ctypes.data, int(warm_gates), int(probe_gates),
-                                                  ctypes.byref(sh), ctypes.byref(wk), ctypes.byref(rate)))
-        return int(sh.value), int(wk.value), float(rate.value)
+                                                  ctypes.byref(sh), ctypes.byref(wk), ctypes.byref(gd),
+                                                  ctypes.byref(rate)))
+        return int(sh.value), int(wk.value), int(gd.value), float(rate.value)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -125,6 +125,7 @@ struct itpp_ctx_s {
   // whose arguments depend only on that order, dtau and the options, are
   // recorded once and replayed.
   bool graphs = true;                // ITPP_OPT_GRAPHS
+  int grid_div = 1;                  // ITPP_OPT_GRID_DIV: gate kernel grid = resident workgroups / grid_div
   hipGraphExec_t step_exec = nullptr;
   std::vector<int> step_pos;         // bit order at the start of the recorded step
   int step_cur = -1, step_par = -1;  // ping-pong slots it starts from
@@ -865,6 +866,8 @@ static itpp_status build_gate(itpp_ctx c, int i, const std::vector<int>& pos, do
     const int q = pos1[t.F[k]];
     gp.qm1[q >> 6] |= 1ull << (q & 63);
   }
+  for (int q = 0; q < kMaxKeyWords; ++q) gp.topm[q] = 0;
+  for (int b = nbits - gp.w; b < nbits; ++b) gp.topm[b >> 6] |= 1ull << (b & 63);
   // packed rep positions and the phase table of the layer kernel
   gp.mvpos = 0;
   for (int m = 0; m < gp.w1; ++m) gp.mvpos |= (uint32_t)gp.mv[m] << (8 * m);
@@ -941,12 +944,12 @@ static itpp_status enqueue_gate(itpp_ctx c, double dtau, bool spec) {
   }
   if (c->shape == 2)
     HIP_TRY(c, launch_layer(c->NW, c->f32, c->real_time, gp, c->side[in], c->side[out], c->plan + pin, c->plan + pout,
-                            c->filt + pin, c->ctl, c->status, c->part, c->cus, c->stream));
+                            c->filt + pin, c->ctl, c->status, c->part, std::max(1, c->cus / c->grid_div), c->stream));
   else
-    HIP_TRY(c, (c->real_time ? launch_gate_rt : launch_gate)(c->NW, c->f32, c->shape, gp, c->side[in], c->side[out],
-                                                             c->plan + pin, c->plan + pout, c->filt + pin, c->ctl,
-                                                             c->status, c->part, c->cus * gate_wgs_per_cu(c->shape),
-                                                             c->stream));
+    HIP_TRY(c, (c->real_time ? launch_gate_rt : launch_gate)(
+                   c->NW, c->f32, c->shape, gp, c->side[in], c->side[out], c->plan + pin, c->plan + pout,
+                   c->filt + pin, c->ctl, c->status, c->part,
+                   std::max(1, c->cus * gate_wgs_per_cu(c->shape) / c->grid_div), c->stream));
   if (c->timing) HIP_TRY(c, hipEventRecord(e1, c->stream));
   HIP_TRY(c, launch_select(c->NW, c->f32, c->side[out], c->plan + pout, c->filt + pin, c->filt + pout, c->plan + pin,
                            c->ctl, c->sel, rp, c->cfg.max_terms, c->cfg.cap_policy == ITPP_CAP_FAIL ? 1 : 0,
@@ -1230,6 +1233,11 @@ itpp_status itpp_set_option(itpp_ctx c, int32_t option, double value) {
     case ITPP_OPT_GRAPHS:
       if (value != 0.0 && value != 1.0) return fail(c, ITPP_ERR_ARG, "graphs must be 0 or 1");
       c->graphs = value != 0.0;
+      return ITPP_OK;
+    case ITPP_OPT_GRID_DIV:
+      if (value != 1.0 && value != 2.0 && value != 4.0 && value != 8.0)
+        return fail(c, ITPP_ERR_ARG, "grid divisor must be 1, 2, 4 or 8");
+      c->grid_div = (int)value;
       return ITPP_OK;
     default:
       return fail(c, ITPP_ERR_ARG, "unknown option");
@@ -1974,54 +1982,78 @@ itpp_status itpp_batch_evolve(itpp_batch b, const double* dtau, const int64_t* n
 }
 
 itpp_status itpp_batch_autotune(itpp_batch b, const double* dtau, int64_t warm_gates, int64_t probe_gates,
-                                int32_t* best_shape, int32_t* best_workers, double* best_rate) {
+                                int32_t* best_shape, int32_t* best_workers, int32_t* best_grid_div,
+                                double* best_rate) {
   if (!b || !dtau || warm_gates < 0 || probe_gates < 1) return ITPP_ERR_ARG;
   const int n = (int)b->inst.size();
   std::vector<double> work(n);
   for (int i = 0; i < n; ++i) work[i] = (double)b->inst[i]->n;
-  // shape choices: bit 0 for one-word keys (n <= 64), bit 1 for two-word keys
-  const int wk[3] = {2, 4, 8};
-  double best = -1.0;
-  int bs = 0, bw = b->workers;
-  for (int sh = 0; sh < 4; ++sh) {
-    for (int w : wk) {
-      for (itpp_ctx c : b->inst) {
-        c->shape = c->NW == 4 ? (sh >> 1) & 1 : sh & 1;
-        drop_step_graph(c);
-        itpp_status s = itpp_reset(c);
-        if (s != ITPP_OK) return batch_fail(b, s, c->err);
-      }
-      itpp_status s = batch_run(b, work, w, [&](int i) {
-        return itpp_evolve_gates(b->inst[i], dtau[i], warm_gates, nullptr);
-      });
-      if (s != ITPP_OK) return s;
-      std::vector<itpp_stats> st(n);
-      const auto t0 = std::chrono::steady_clock::now();
-      s = batch_run(b, work, w, [&](int i) {
-        return itpp_evolve_gates(b->inst[i], dtau[i], probe_gates, &st[i]);
-      });
-      if (s != ITPP_OK) return s;
-      const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-      double tu = 0.0;
-      for (const auto& x : st) tu += x.term_updates;
-      const double rate = dt > 0.0 ? tu / dt : 0.0;
-      if (rate > best) {
-        best = rate;
-        bs = sh;
-        bw = w;
-      }
+  // one setting: gate shapes (one for n <= 64, one above), workers, grid divisor
+  struct Setting {
+    int s_small, s_large, workers, grid_div;
+  };
+  auto apply = [&](const Setting& x) -> itpp_status {
+    for (itpp_ctx c : b->inst) {
+      c->shape = c->NW == 4 ? x.s_large : x.s_small;
+      c->grid_div = x.grid_div;
+      drop_step_graph(c);
+      itpp_status s = itpp_reset(c);
+      if (s != ITPP_OK) return batch_fail(b, s, c->err);
     }
+    return ITPP_OK;
+  };
+  auto probe = [&](const Setting& x, double* rate) -> itpp_status {
+    itpp_status s = apply(x);
+    if (s != ITPP_OK) return s;
+    s = batch_run(b, work, x.workers, [&](int i) { return itpp_evolve_gates(b->inst[i], dtau[i], warm_gates, nullptr); });
+    if (s != ITPP_OK) return s;
+    std::vector<itpp_stats> st(n);
+    const auto t0 = std::chrono::steady_clock::now();
+    s = batch_run(b, work, x.workers, [&](int i) { return itpp_evolve_gates(b->inst[i], dtau[i], probe_gates, &st[i]); });
+    if (s != ITPP_OK) return s;
+    const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    double tu = 0.0;
+    for (const auto& y : st) tu += y.term_updates;
+    *rate = dt > 0.0 ? tu / dt : 0.0;
+    return ITPP_OK;
+  };
+  // coordinate descent: the shape pair first, then workers, then the grid
+  Setting best{1, 1, b->workers, 1};
+  double best_r = -1.0;
+  auto consider = [&](const Setting& x) -> itpp_status {
+    double r = 0.0;
+    itpp_status s = probe(x, &r);
+    if (s != ITPP_OK) return s;
+    if (r > best_r) {
+      best_r = r;
+      best = x;
+    }
+    return ITPP_OK;
+  };
+  const Setting start = best;
+  for (int ss = 0; ss < 3; ++ss)
+    for (int sl = 0; sl < 3; ++sl) {
+      itpp_status s = consider(Setting{ss, sl, start.workers, start.grid_div});
+      if (s != ITPP_OK) return s;
+    }
+  const Setting after_shapes = best;
+  for (int w : {2, 4, 8, 16}) {
+    if (w == after_shapes.workers) continue;
+    itpp_status s = consider(Setting{after_shapes.s_small, after_shapes.s_large, w, after_shapes.grid_div});
+    if (s != ITPP_OK) return s;
   }
-  for (itpp_ctx c : b->inst) {
-    c->shape = c->NW == 4 ? (bs >> 1) & 1 : bs & 1;
-    drop_step_graph(c);
-    itpp_status s = itpp_reset(c);
-    if (s != ITPP_OK) return batch_fail(b, s, c->err);
+  const Setting after_workers = best;
+  for (int g : {2, 4, 8}) {
+    itpp_status s = consider(Setting{after_workers.s_small, after_workers.s_large, after_workers.workers, g});
+    if (s != ITPP_OK) return s;
   }
-  b->workers = bw;
-  if (best_shape) *best_shape = bs;
-  if (best_workers) *best_workers = bw;
-  if (best_rate) *best_rate = best;
+  itpp_status s = apply(best);
+  if (s != ITPP_OK) return s;
+  b->workers = best.workers;
+  if (best_shape) *best_shape = best.s_small + 3 * best.s_large;
+  if (best_workers) *best_workers = best.workers;
+  if (best_grid_div) *best_grid_div = best.grid_div;
+  if (best_rate) *best_rate = best_r;
   return ITPP_OK;
 }
 

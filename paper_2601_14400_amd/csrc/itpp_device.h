@@ -77,6 +77,14 @@ __device__ __forceinline__ Key<NW> xor_top(Key<NW> k, int nbits, int w) {
   return k;
 }
 
+// Key xor a uniform mask (a gate's flip bits, precomputed per gate).
+template <int NW>
+__device__ __forceinline__ Key<NW> xor_mask(Key<NW> k, const uint64_t* m) {
+#pragma unroll
+  for (int i = 0; i < NW; ++i) k.w[i] ^= m[i];
+  return k;
+}
+
 // Class = pattern of the w most significant meaningful bits.
 template <int NW>
 __device__ __forceinline__ int class_of(const Key<NW>& k, int nbits, int w) {
@@ -339,6 +347,16 @@ __device__ inline ClassView make_view(const Plan* __restrict__ pp, int cls) {
   for (int c = 1; c < kMaxClasses; ++c)
     if (c >= nc) v.start[c] = acc;
   return v;
+}
+
+// e mod 4 of Q P = i^e R read from the gate's table over the (x, z) bits of
+// P on the support of Q (nph = 2 or 4 such bits, rep positions one per byte
+// of phpos).
+template <int NW>
+__device__ __forceinline__ uint32_t phase_e(const Key<NW>& k, uint32_t phpos, uint32_t etab, uint32_t nph) {
+  uint32_t idx = bit_at(k, phpos & 0xffu) | (bit_at(k, (phpos >> 8) & 0xffu) << 1);
+  if (nph > 2) idx |= (bit_at(k, (phpos >> 16) & 0xffu) << 2) | (bit_at(k, phpos >> 24) << 3);
+  return (etab >> (2 * idx)) & 3u;
 }
 
 // Phase of Q P = sigma R for a commuting P: +1 or -1 (sigma_neg = 1 for -1).

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void partition_kernel(GateParams gp, Side in, 
     bool pred = false;
     if (active && i < hi) {
       Key<NW> a = load_key<NW>(in, VA.phys(i));
-      Key<NW> bb = xor_top(load_key<NW>(in, VB.phys(d - i - 1)), nbits, w);
+      Key<NW> bb = xor_mask(load_key<NW>(in, VB.phys(d - i - 1)), gp.topm);
       pred = !key_less(bb, a);  // A[i] <= B'[d-i-1]: the answer is above i
     }
     const uint64_t mask = __ballot(pred);
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256) void partition_kernel(GateParams gp, Side in, 
     uint64_t i = lo, jj = d - lo;
     if (i > 0 && jj < nB) {
       Key<NW> a = load_key<NW>(in, VA.phys(i - 1));
-      Key<NW> bb = xor_top(load_key<NW>(in, VB.phys(jj)), nbits, w);
+      Key<NW> bb = xor_mask(load_key<NW>(in, VB.phys(jj)), gp.topm);
       if (key_eq(a, bb)) jj += 1;
     }
     part[2 * b] = i;
@@ -455,7 +455,7 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
       const bool sv = survives(k, (double)cs, fin, gp.pos_in, nbits);
       bool comm = !anticommutes(k, gp);
       if constexpr (RT) comm = !comm;  // the strings that branch
-      if (!isA) k = xor_top(k, nbits, w);  // B' = B xor Q lives in class cA's key space
+      if (!isA) k = xor_mask(k, gp.topm);  // B' = B xor Q lives in class cA's key space
 #pragma unroll
       for (int q = 0; q < NW; ++q) sm.key[q][x] = k.w[q];
       sm.coef[x] = normalised<T>(cs, fin.cI);
@@ -509,10 +509,11 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
             const bool paired = (y >= 0) && (sm.info[y] & 1);
             const T c = sm.coef[x];
             const T cp = paired ? sm.coef[y] : (T)0;
-            const Key<NW> ownk = isA ? k : xor_top(k, nbits, w);
+            const Key<NW> ownk = isA ? k : xor_mask(k, gp.topm);
             bool neg = false;
-            if (comm) {
-              const int e4 = phase_negative(ownk, gp);
+            const uint32_t nph = (gp.lflags >> 6) & 7u;
+            if (comm && nph) {
+              const int e4 = (int)phase_e(ownk, gp.phpos, gp.etab, nph);
               if constexpr (RT) {
                 // i Q P = i^(k+1) R: the own branch is -sin c for k = 1 and
                 // +sin c for k = 3; the partner's branch (its phase is i^-k)
@@ -533,8 +534,8 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
               inf |= 4u;
               sm.partner[x] = (uint16_t)y;
             }
-            int es = 0;
-            for (int mm = 0; mm < gp.w1; ++mm) es |= get_bit(ownk, gp.epos[mm]) << mm;
+            int es = (int)bit_at(ownk, (gp.fgpos >> 16) & 0xffu);
+            if (gp.w1 > 1) es |= (int)bit_at(ownk, gp.fgpos >> 24) << 1;
             // A: self -> stream cA, branch -> stream cB; B: the reverse
             uint64_t sinc = 0, binc = 0;
             if (hs) {
@@ -759,9 +760,11 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
         uint32_t bb;
         Key<NW> mk = move_bit(k, gp.mvpos & 0xffu, (uint32_t)nbits - 1u, bb);
         if (gp.w1 > 1) mk = move_bit(mk, (gp.mvpos >> 8) & 0xffu, (uint32_t)nbits - 1u, bb);
-        const Key<NW> ownk = x < nAt ? k : xor_top(k, nbits, w);
+        const Key<NW> ownk = x < nAt ? k : xor_mask(k, gp.topm);
+        const uint32_t w2 = (gp.lflags >> 4) & 3u;
         int fself = 0;
-        for (int bq = 0; bq < gp.w2; ++bq) fself |= get_bit(ownk, gp.fposg[bq]) << bq;
+        if (w2 > 0) fself = (int)bit_at(ownk, gp.fgpos & 0xffu);
+        if (w2 > 1) fself |= (int)bit_at(ownk, (gp.fgpos >> 8) & 0xffu) << 1;
 #pragma unroll
         for (int q = 0; q < NW; ++q) sm.key[q][x] = mk.w[q];
         sm.info[x] = (uint16_t)(inf | (fself << 10));

@@ -172,6 +172,7 @@ struct GateParams {
   int32_t spec;              // 1: write only outputs above a margin below the predicted K-th value
   int32_t spos;              // schedule position (index of kth_ratio), -1: none
   uint64_t qm1[kMaxKeyWords];    // this gate's flip mask in the next rep (branch key = self key ^ qm1)
+  uint64_t topm[kMaxKeyWords];   // this gate's flip mask in the current rep (the w top bits)
   double spec_mult;          // that margin as a factor of the predicted value
   int32_t tile;              // merged elements per tile
   uint32_t check_write_threshold;

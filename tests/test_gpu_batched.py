@@ -76,14 +76,24 @@ def test_gate_shape_1_matches_shape_0(builder, steps):
 def test_autotune_then_evolve():
     ws = small_instances(count=6, K=2000)
     b = P.batch_for(ws)
-    shape, workers, rate = b.autotune([w.dtau for w in ws], 30, 30)
-    assert shape in (0, 1, 2, 3) and workers in (2, 4, 8) and rate > 0
+    shape, workers, grid_div, rate = b.autotune([w.dtau for w in ws], 30, 30)
+    assert 0 <= shape < 9 and workers in (2, 4, 8, 16) and grid_div in (1, 2, 4, 8) and rate > 0
     steps = [2] * len(ws)
     b.evolve([w.dtau for w in ws], steps)
     ref = single_states(ws, steps)
     for i, e in enumerate(b.instances):
         assert e.state() == ref[i]
     b.close()
+
+
+@pytest.mark.parametrize("shape,grid_div", [(0, 8), (1, 4), (2, 2)])
+def test_grid_divisor_keeps_results(shape, grid_div):
+    """A smaller gate-kernel grid (fewer workgroups taking the same tiles)
+    changes no result, for every shape."""
+    w = W.config2(K=4096)
+    a = single_states([w], [3], gate_shape=shape)[0]
+    b = single_states([w], [3], gate_shape=shape, grid_div=grid_div)[0]
+    assert a == b
 
 
 def test_batch_errors():
