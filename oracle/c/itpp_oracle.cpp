@@ -15,7 +15,11 @@
 //     strings, to the identity plus the K-1 largest |c| with ties broken by
 //     the smaller (X, Z) bit integers (K-truncation, Sec. II.C);
 //   * every coefficient is then divided by the identity coefficient
-//     (normalisation after every elementary gate, Sec. II.C).
+//     (normalisation after every elementary gate, Sec. II.C);
+//   * with a Pauli-weight cutoff set (itpp_oracle_set_max_weight, the second
+//     truncation rule of Sec. II.B), strings with more non-identity letters
+//     than the cutoff are dropped together with the threshold, before the
+//     cap (the reading of the Python oracle).
 // cosh/sinh come from the C library once per gate, so results agree bit for
 // bit with the Python oracle.
 //
@@ -77,7 +81,14 @@ struct Oracle {
   std::string err;
   double term_updates = 0.0;
   long long gates = 0;
+  int max_weight = 0;  // 0: no weight cutoff
 };
+
+int pauli_weight(const std::string& P) {
+  int w = 0;
+  for (char a : P) w += a != 'I';
+  return w;
+}
 
 template <typename T>
 std::unordered_map<std::string, T>& state(Oracle* o);
@@ -148,7 +159,8 @@ int one_gate(Oracle* o, std::unordered_map<std::string, T>& S, const std::string
   std::vector<std::pair<std::string, T>> kept;
   kept.reserve(out.size());
   for (auto& kv : out)
-    if ((double)std::fabs(kv.second) > delta) kept.emplace_back(kv.first, kv.second);
+    if ((double)std::fabs(kv.second) > delta && (o->max_weight <= 0 || pauli_weight(kv.first) <= o->max_weight))
+      kept.emplace_back(kv.first, kv.second);
   // truncate: cap
   if ((long long)kept.size() > K) {
     T cI = 0;
@@ -391,6 +403,9 @@ void* itpp_oracle_new32(int n) {
 }
 
 void itpp_oracle_free(void* h) { delete static_cast<Oracle*>(h); }
+
+// Pauli-weight cutoff for the following gates (0: none).
+void itpp_oracle_set_max_weight(void* h, int max_weight) { static_cast<Oracle*>(h)->max_weight = max_weight; }
 
 const char* itpp_oracle_error(void* h) { return static_cast<Oracle*>(h)->err.c_str(); }
 

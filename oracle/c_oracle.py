@@ -43,6 +43,8 @@ def _load():
                                            ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_double, ctypes.c_longlong,
                                            ctypes.c_double, ctypes.c_longlong]
+        lib.itpp_oracle_set_max_weight.restype = None
+        lib.itpp_oracle_set_max_weight.argtypes = [ctypes.c_void_p, ctypes.c_int]
         lib.itpp_oracle_size.restype = ctypes.c_longlong
         lib.itpp_oracle_size.argtypes = [ctypes.c_void_p]
         lib.itpp_oracle_term_updates.restype = ctypes.c_double
@@ -90,6 +92,10 @@ class COracle:
                                           int(n_steps), float(delta), int(K))
         if rc != 0:
             raise RuntimeError(self._lib.itpp_oracle_error(self._h).decode())
+
+    def set_max_weight(self, max_weight: int) -> None:
+        """Pauli-weight cutoff of the following gates (0: none)."""
+        self._lib.itpp_oracle_set_max_weight(self._h, int(max_weight))
 
     def size(self) -> int:
         return int(self._lib.itpp_oracle_size(self._h))
@@ -162,8 +168,10 @@ class COracle:
         return L.value, da, dd.value, dth[:G]
 
 
-def run_workload(w, n_steps=None, K=None, precision=None) -> COracle:
+def run_workload(w, n_steps=None, K=None, precision=None, max_weight=0) -> COracle:
     o = COracle(w.n, precision or w.precision)
+    if max_weight:
+        o.set_max_weight(max_weight)
     o.evolve(w.strings, w.alphas, w.schedule, w.dtau, w.n_steps if n_steps is None else n_steps,
              w.delta, w.K if K is None else K)
     return o

@@ -108,3 +108,43 @@ def pauli_coefficients(rho: np.ndarray, tol: float = 0.0) -> Dict[str, float]:
 
 def expectation(rho: np.ndarray, O: np.ndarray) -> float:
     return float(np.real(np.trace(O @ rho)))
+
+
+def weight_projected_trotter(strings: Sequence[str], alphas: Sequence[float],
+                             schedule: Sequence[Tuple[int, float]], dtau: float, n_steps: int,
+                             max_weight: int) -> Dict[str, float]:
+    """Trotter product applied gate by gate to rho = I with the Pauli-weight
+    cutoff of Sec. II.B after every gate, as a linear projection: rho ->
+    V rho V (V = exp(-(theta/2) Q) by the matrix exponential), then
+    rho -> 2^-n sum over P of weight <= max_weight of Tr(P rho) P.  Returns
+    the coefficients a_P = Tr(P rho) / Tr(rho) of the final state (the
+    projection is linear, so normalising once at the end equals normalising
+    after every gate)."""
+    n = len(strings[0])
+    dim = 2 ** n
+    letters = "IXYZ"
+    basis = []
+    for idx in range(4 ** n):
+        P = "".join(letters[(idx >> (2 * j)) & 3] for j in range(n))
+        if sum(1 for a in P if a != "I") <= max_weight:
+            basis.append((P, pauli_matrix(P)))
+    rho = np.eye(dim, dtype=complex)
+    for _ in range(n_steps):
+        for k, m in schedule:
+            Q = strings[k]
+            if Q == "I" * n:
+                continue
+            V = gate_matrix(Q, alphas[k] * m * dtau)
+            rho = V @ rho @ V
+            proj = np.zeros_like(rho)
+            for P, M in basis:
+                proj += (np.trace(M @ rho) / dim) * M
+            rho = proj
+    tr = np.trace(rho).real
+    out: Dict[str, float] = {}
+    for P, M in basis:
+        a = np.trace(M @ rho) / tr
+        if abs(a.imag) > 1e-9:
+            raise ValueError("imaginary Pauli coefficient")
+        out[P] = float(a.real)
+    return out

@@ -21,6 +21,12 @@ Plain, slow and meant to be checked by eye against the paper
   normalisation of Algorithm 1 done after every elementary step as Sec. II.C
   prescribes.
 
+Optional Pauli-weight cutoff (``max_weight``, the second truncation rule of
+Sec. II.B): a string of weight (number of non-identity letters) above the
+cutoff is dropped.  Reading: it is applied with the coefficient threshold
+after every gate, before the cap selection, so the K kept strings are the
+largest of those within the cutoff; the identity (weight 0) always passes.
+
 Readings fixed here where the paper leaves a choice open:
 * ``Q P`` multiplies with ``Q`` on the left, using ``XY = iZ``, ``YZ = iX``,
   ``ZX = iY``; for commuting strings ``Q P = sign * R`` with ``sign = +-1``.
@@ -143,10 +149,17 @@ def apply_gate_f32(S: Dict[str, np.float32], Q: str, ch: float, sh: float) -> Di
     return out
 
 
-def truncate(S: Dict[str, float], delta: float, K: int) -> Dict[str, float]:
-    """Keep ``|c| > delta``; if more than ``K`` remain keep the identity and
-    the ``K-1`` other strings of largest ``|c|`` (ties: smaller (X, Z))."""
-    kept = {P: c for P, c in S.items() if abs(float(c)) > delta}
+def pauli_weight(P: str) -> int:
+    """Number of non-identity letters (Sec. II.B)."""
+    return sum(1 for a in P if a != "I")
+
+
+def truncate(S: Dict[str, float], delta: float, K: int, max_weight: Optional[int] = None) -> Dict[str, float]:
+    """Keep ``|c| > delta`` (and, with a cutoff, Pauli weight <= max_weight);
+    if more than ``K`` remain keep the identity and the ``K-1`` other strings
+    of largest ``|c|`` (ties: smaller (X, Z))."""
+    kept = {P: c for P, c in S.items()
+            if abs(float(c)) > delta and (max_weight is None or pauli_weight(P) <= max_weight)}
     if len(kept) <= K:
         return kept
     n = len(next(iter(kept)))
@@ -186,7 +199,7 @@ def evolve(n: int, strings: Sequence[str], alphas: Sequence[float],
            schedule: Sequence[Tuple[int, float]], dtau: float, n_steps: int,
            delta: float, K: int, S0: Optional[Dict[str, float]] = None,
            on_gate: Optional[Callable[[int, Dict[str, float], float], None]] = None,
-           precision: str = "f64") -> Tuple[Dict[str, float], Dict[str, float]]:
+           precision: str = "f64", max_weight: Optional[int] = None) -> Tuple[Dict[str, float], Dict[str, float]]:
     """Algorithm 1 with per-gate truncation and normalisation.
 
     Returns ``(S, stats)`` with ``stats['term_updates']`` = sum over gates of
@@ -212,11 +225,11 @@ def evolve(n: int, strings: Sequence[str], alphas: Sequence[float],
             updates += len(S)
             if f32:
                 Sp = apply_gate_f32(S, Q, ch, sh)
-                St = truncate(Sp, delta, K)
+                St = truncate(Sp, delta, K, max_weight)
                 S, cI = normalize_f32(St, n)
             else:
                 Sp = apply_gate(S, Q, ch, sh)
-                St = truncate(Sp, delta, K)
+                St = truncate(Sp, delta, K, max_weight)
                 S, cI = normalize(St, n)
             if on_gate is not None:
                 on_gate(g, S, cI)
