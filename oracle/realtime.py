@@ -36,10 +36,12 @@ def apply_gate_real(S: Dict[str, float], Q: str, cs: float, sn: float) -> Dict[s
 
 def evolve_real(S0: Dict[str, float], strings: Sequence[str], alphas: Sequence[float],
                 schedule: Sequence[Tuple[int, float]], dt: float, n_steps: int, delta: float,
-                K: int) -> Tuple[Dict[str, float], float]:
+                K: int, max_weight=None) -> Tuple[Dict[str, float], float]:
     """First-order (or any scheduled) Trotter steps of real-time propagation
     from S0 with angle theta = alpha_k * m * dt per gate, truncated after
-    every gate like the imaginary-time oracle.  Returns (S, term updates)."""
+    every gate like the imaginary-time oracle (threshold, optional Pauli
+    weight cutoff, cap: both truncation rules of Sec. II.B are stated for
+    real-time propagation).  Returns (S, term updates)."""
     S = dict(S0)
     n = len(next(iter(S)))
     updates = 0.0
@@ -50,5 +52,5 @@ def evolve_real(S0: Dict[str, float], strings: Sequence[str], alphas: Sequence[f
                 continue
             th = alphas[k] * m * dt
             updates += len(S)
-            S = truncate(apply_gate_real(S, Q, math.cos(th), math.sin(th)), delta, K)
+            S = truncate(apply_gate_real(S, Q, math.cos(th), math.sin(th)), delta, K, max_weight)
     return S, updates
