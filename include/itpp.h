@@ -314,14 +314,24 @@ itpp_status itpp_num_gates(itpp_ctx ctx, int64_t* out);
  *    workgroups that fit on the device at once divided by this (its tiles
  *    are taken from a ticket counter, so any grid covers every tile).
  *    Smaller grids leave room for the kernels of other contexts running
- *    concurrently (the batch); results do not depend on it. */
+ *    concurrently (the batch); results do not depend on it.
+ *  ITPP_OPT_MAX_WEIGHT (default 0 = none; an integer in [0, n]): the Pauli
+ *    weight cutoff of Sec. II.B.  From the next gate on, an output string
+ *    with more non-identity letters than the cutoff is dropped, with the
+ *    coefficient threshold and before the cap selection (the K kept strings
+ *    are the largest within the cutoff; the identity always passes).  The
+ *    strings of the current state are not filtered until a gate produces
+ *    them.  Gates of shape 2 run on shape 1 while a cutoff is set.  Not
+ *    available with the reverse sweep (ITPP_ERR_STATE with checkpoints
+ *    set, and itpp_set_adjoint refuses while a cutoff is set). */
 typedef enum {
   ITPP_OPT_SPECULATION = 1,
   ITPP_OPT_SPEC_MARGIN = 2,
   ITPP_OPT_GATE_SHAPE = 3,
   ITPP_OPT_REAL_TIME = 4,
   ITPP_OPT_GRAPHS = 5,
-  ITPP_OPT_GRID_DIV = 6
+  ITPP_OPT_GRID_DIV = 6,
+  ITPP_OPT_MAX_WEIGHT = 7
 } itpp_option;
 itpp_status itpp_set_option(itpp_ctx ctx, int32_t option, double value);
 

@@ -304,7 +304,7 @@ class Engine:
 
     def set_option(self, name: str, value: float):
         opt = {"speculation": 1, "spec_margin": 2, "gate_shape": 3, "real_time": 4, "graphs": 5,
-               "grid_div": 6}[name]
+               "grid_div": 6, "max_weight": 7}[name]
         self._check(self._lib.itpp_set_option(self._h, opt, float(value)))
 
     def set_timing(self, enable: bool = True):

@@ -126,6 +126,7 @@ struct itpp_ctx_s {
   // recorded once and replayed.
   bool graphs = true;                // ITPP_OPT_GRAPHS
   int grid_div = 1;                  // ITPP_OPT_GRID_DIV: gate kernel grid = resident workgroups / grid_div
+  int max_weight = 0;                // ITPP_OPT_MAX_WEIGHT: Pauli-weight cutoff (0: none)
   hipGraphExec_t step_exec = nullptr;
   std::vector<int> step_pos;         // bit order at the start of the recorded step
   int step_cur = -1, step_par = -1;  // ping-pong slots it starts from
@@ -868,6 +869,18 @@ static itpp_status build_gate(itpp_ctx c, int i, const std::vector<int>& pos, do
   }
   for (int q = 0; q < kMaxKeyWords; ++q) gp.topm[q] = 0;
   for (int b = nbits - gp.w; b < nbits; ++b) gp.topm[b >> 6] |= 1ull << (b & 63);
+  // weight change of the branch Q P over P for every support pattern of P
+  gp.wmax = c->max_weight;
+  gp.pad_wmax = 0;
+  gp.wtab = 0;
+  for (uint32_t idx = 0; idx < 16; ++idx) {
+    int dw = 0;
+    for (int j = 0; j < t.nsup && j < 2; ++j) {
+      const int xp = (idx >> (2 * j)) & 1, zp = (idx >> (2 * j + 1)) & 1;
+      dw += ((xp ^ t.qx[j]) | (zp ^ t.qz[j])) - (xp | zp);
+    }
+    gp.wtab |= (uint64_t)(dw + 2) << (3 * idx);
+  }
   // packed rep positions and the phase table of the layer kernel
   gp.mvpos = 0;
   for (int m = 0; m < gp.w1; ++m) gp.mvpos |= (uint32_t)gp.mv[m] << (8 * m);
@@ -929,7 +942,9 @@ static itpp_status enqueue_gate(itpp_ctx c, double dtau, bool spec) {
   GateParams gp;
   std::vector<int> pos1;
   RepPos rp;
-  itpp_status bs = build_gate(c, i, c->pos, dtau, spec, c->shape, gp, pos1, rp);
+  // the layer kernel (shape 2) has no weight cutoff: such gates run on shape 1
+  const int shape = (c->shape == 2 && c->max_weight > 0) ? 1 : c->shape;
+  itpp_status bs = build_gate(c, i, c->pos, dtau, spec, shape, gp, pos1, rp);
   if (bs != ITPP_OK) return bs;
   const int in = c->cur, out = c->cur ^ 1;
   const int pin = c->par, pout = c->par ^ 1;
@@ -942,14 +957,14 @@ static itpp_status enqueue_gate(itpp_ctx c, double dtau, bool spec) {
     HIP_TRY(c, next_event(c, &e2));
     HIP_TRY(c, hipEventRecord(e0, c->stream));
   }
-  if (c->shape == 2)
+  if (shape == 2)
     HIP_TRY(c, launch_layer(c->NW, c->f32, c->real_time, gp, c->side[in], c->side[out], c->plan + pin, c->plan + pout,
                             c->filt + pin, c->ctl, c->status, c->part, std::max(1, c->cus / c->grid_div), c->stream));
   else
     HIP_TRY(c, (c->real_time ? launch_gate_rt : launch_gate)(
-                   c->NW, c->f32, c->shape, gp, c->side[in], c->side[out], c->plan + pin, c->plan + pout,
+                   c->NW, c->f32, shape, gp, c->side[in], c->side[out], c->plan + pin, c->plan + pout,
                    c->filt + pin, c->ctl, c->status, c->part,
-                   std::max(1, c->cus * gate_wgs_per_cu(c->shape) / c->grid_div), c->stream));
+                   std::max(1, c->cus * gate_wgs_per_cu(shape) / c->grid_div), c->stream));
   if (c->timing) HIP_TRY(c, hipEventRecord(e1, c->stream));
   HIP_TRY(c, launch_select(c->NW, c->f32, c->side[out], c->plan + pout, c->filt + pin, c->filt + pout, c->plan + pin,
                            c->ctl, c->sel, rp, c->cfg.max_terms, c->cfg.cap_policy == ITPP_CAP_FAIL ? 1 : 0,
@@ -1233,6 +1248,12 @@ itpp_status itpp_set_option(itpp_ctx c, int32_t option, double value) {
     case ITPP_OPT_GRAPHS:
       if (value != 0.0 && value != 1.0) return fail(c, ITPP_ERR_ARG, "graphs must be 0 or 1");
       c->graphs = value != 0.0;
+      return ITPP_OK;
+    case ITPP_OPT_MAX_WEIGHT:
+      if (!(value >= 0.0) || value > (double)c->n || value != std::floor(value))
+        return fail(c, ITPP_ERR_ARG, "weight cutoff must be an integer in [0, n]");
+      if (value > 0.0 && c->ckpt_every > 0) return fail(c, ITPP_ERR_STATE, "the reverse sweep has no weight cutoff");
+      c->max_weight = (int)value;
       return ITPP_OK;
     case ITPP_OPT_GRID_DIV:
       if (value != 1.0 && value != 2.0 && value != 4.0 && value != 8.0)
@@ -1755,6 +1776,7 @@ itpp_status itpp_set_adjoint(itpp_ctx c, int32_t every_steps, int64_t workspace_
   if (!c) return ITPP_ERR_ARG;
   if (every_steps < 0 || workspace_bytes < 0) return fail(c, ITPP_ERR_ARG, "negative argument");
   if (every_steps > 0 && c->f32) return fail(c, ITPP_ERR_ARG, "the reverse sweep needs ITPP_F64 coefficients");
+  if (every_steps > 0 && c->max_weight > 0) return fail(c, ITPP_ERR_STATE, "the reverse sweep has no weight cutoff");
   c->ckpt_every = every_steps;
   c->adj_workspace = workspace_bytes;
   free_ckpts(c);

@@ -349,14 +349,30 @@ __device__ inline ClassView make_view(const Plan* __restrict__ pp, int cls) {
   return v;
 }
 
-// e mod 4 of Q P = i^e R read from the gate's table over the (x, z) bits of
-// P on the support of Q (nph = 2 or 4 such bits, rep positions one per byte
-// of phpos).
+// Pattern of the (x, z) bits of P on the support of Q (nb = 2 or 4 bits,
+// rep positions one per byte of phpos): the index of the gate's tables.
+template <int NW>
+__device__ __forceinline__ uint32_t support_pattern(const Key<NW>& k, uint32_t phpos, uint32_t nb) {
+  uint32_t idx = bit_at(k, phpos & 0xffu) | (bit_at(k, (phpos >> 8) & 0xffu) << 1);
+  if (nb > 2) idx |= (bit_at(k, (phpos >> 16) & 0xffu) << 2) | (bit_at(k, phpos >> 24) << 3);
+  return idx;
+}
+
+// e mod 4 of Q P = i^e R read from the gate's table over the support
+// pattern of P (nph = 2 or 4 bits).
 template <int NW>
 __device__ __forceinline__ uint32_t phase_e(const Key<NW>& k, uint32_t phpos, uint32_t etab, uint32_t nph) {
-  uint32_t idx = bit_at(k, phpos & 0xffu) | (bit_at(k, (phpos >> 8) & 0xffu) << 1);
-  if (nph > 2) idx |= (bit_at(k, (phpos >> 16) & 0xffu) << 2) | (bit_at(k, phpos >> 24) << 3);
-  return (etab >> (2 * idx)) & 3u;
+  return (etab >> (2 * support_pattern(k, phpos, nph))) & 3u;
+}
+
+// Pauli weight (non-identity letters, Sec. II.B) of a key in a rep whose
+// canonical bit b sits at rep position pos[b] (x bits of qubits 0..n-1,
+// then their z bits).
+template <int NW>
+__device__ __forceinline__ uint32_t pauli_weight(const Key<NW>& k, const uint8_t* pos, int n) {
+  uint32_t w = 0;
+  for (int i = 0; i < n; ++i) w += bit_at(k, pos[i]) | bit_at(k, pos[n + i]);
+  return w;
 }
 
 // Phase of Q P = sigma R for a commuting P: +1 or -1 (sigma_neg = 1 for -1).

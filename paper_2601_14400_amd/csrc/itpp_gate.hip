@@ -455,6 +455,9 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
       const bool sv = survives(k, (double)cs, fin, gp.pos_in, nbits);
       bool comm = !anticommutes(k, gp);
       if constexpr (RT) comm = !comm;  // the strings that branch
+      // with a weight cutoff, the string's weight waits in rb[x] until the
+      // walk reads it (the walk writes rb[x] only after that)
+      if (gp.wmax) sm.rb[x] = (uint16_t)pauli_weight(k, gp.pos_in, nbits >> 1);
       if (!isA) k = xor_mask(k, gp.topm);  // B' = B xor Q lives in class cA's key space
 #pragma unroll
       for (int q = 0; q < NW; ++q) sm.key[q][x] = k.w[q];
@@ -528,8 +531,17 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
             }
             T vs, vb;
             values_from<T>(c, comm, paired, cp, neg, ch, sh, vs, vb);
-            const bool hs = abs_d(vs) > tw;
-            const bool hb = comm && !paired && abs_d(vb) > tw;
+            bool hs = abs_d(vs) > tw;
+            bool hb = comm && !paired && abs_d(vb) > tw;
+            if (gp.wmax) {
+              // weight cutoff (Sec. II.B): the self output keeps the
+              // string's weight, the branch changes it on the support of Q
+              const uint32_t wp = sm.rb[x];
+              const uint32_t pat = support_pattern(ownk, gp.phpos, 2u * (uint32_t)gp.nsup);
+              const uint32_t wr = wp + (uint32_t)((gp.wtab >> (3 * pat)) & 7u) - 2u;
+              hs = hs && wp <= (uint32_t)gp.wmax;
+              hb = hb && wr <= (uint32_t)gp.wmax;
+            }
             if (paired) {
               inf |= 4u;
               sm.partner[x] = (uint16_t)y;

@@ -173,6 +173,9 @@ struct GateParams {
   int32_t spos;              // schedule position (index of kth_ratio), -1: none
   uint64_t qm1[kMaxKeyWords];    // this gate's flip mask in the next rep (branch key = self key ^ qm1)
   uint64_t topm[kMaxKeyWords];   // this gate's flip mask in the current rep (the w top bits)
+  int32_t wmax;              // Pauli-weight cutoff (0: none)
+  int32_t pad_wmax;
+  uint64_t wtab;             // weight(Q P) - weight(P) + 2 for the 16 support patterns (3 bits each)
   double spec_mult;          // that margin as a factor of the predicted value
   int32_t tile;              // merged elements per tile
   uint32_t check_write_threshold;
