@@ -904,9 +904,11 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
 // Host launchers.
 // Gate kernel shapes (threads per workgroup, merged elements per tile for
 // one- and two-word keys).  Shape 0: one 1024-thread workgroup per CU with
-// large tiles (large states); shape 1: two 512-thread workgroups per CU with
-// half-size tiles (more tiles in flight for small states).  The tile LDS of
-// either shape fits the CU's 160 KB at its occupancy.
+// 4000/2000-string tiles; shape 1 (the default): two 512-thread workgroups
+// per CU, each with the largest one-word tile whose LDS (about 32 B per
+// string) still lets two share the CU's 160 KB, and 1500-string tiles for
+// two-word keys.  Larger tiles pay the per-tile ticket, barriers and
+// look-back less often.
 template <int SHAPE>
 struct GateShape;
 template <>
@@ -922,7 +924,7 @@ struct GateShape<1> {
   static constexpr int block = 512, wgs_per_cu = 2;
   template <int NW>
   static constexpr int tile() {
-    return NW == 2 ? 2000 : 1500;
+    return NW == 2 ? 2380 : 1500;
   }
 };
 
