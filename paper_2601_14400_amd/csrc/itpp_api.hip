@@ -134,6 +134,7 @@ struct itpp_ctx_s {
   std::vector<HostSnap> step_snaps;  // host state before each of its gates (serial relative)
   std::vector<int> last_step_pos;    // bit order at the start of the previous step
   int64_t graph_steps = 0;           // steps run as graph replays (statistics)
+  int short_batches = 0;             // batches left at kSyncAfterHalt gates
   // The null stream cannot be captured: with cfg.stream == NULL the gates
   // run on a private non-blocking stream joined to the null stream by events
   // before and after (so they stay ordered with the caller's work).
@@ -146,6 +147,11 @@ namespace {
 const char* kVersion = "itpp gfx950 merge-join engine 0.2";
 // Host synchronisation period (gates) for the speculation check.
 constexpr int64_t kSyncEvery = 512;
+// After a speculative gate had to be redone, the next few batches are short:
+// a redone gate turns the rest of its batch into launches that return at
+// once, and failures come in runs (when the cap starts to bind).
+constexpr int64_t kSyncAfterHalt = 48;
+constexpr int kShortBatchesAfterHalt = 8;
 thread_local std::string g_create_error = "no error";
 
 // Device scratch of itpp_expect_squared_noalloc: the observable words and
@@ -1108,6 +1114,10 @@ static itpp_status run_gates_on(itpp_ctx c, double dtau, int64_t n_gates, itpp_s
     // with step graphs, batches end on step boundaries
     const int64_t span = can_graph ? (G - c->gpos) % G + std::max<int64_t>(1, kSyncEvery / GR) * GR : kSyncEvery;
     int64_t batch = std::min<int64_t>(n_gates - done, span);
+    if (c->short_batches > 0) {
+      batch = std::min<int64_t>(batch, kSyncAfterHalt);
+      --c->short_batches;
+    }
     if (E > 0 && c->fwd_valid) {
       // forward checkpoint of the state before gate fwd_gates, every E gates
       if (c->fwd_gates % E == 0 && (int64_t)c->ckpts.size() == c->fwd_gates / E) {
@@ -1184,6 +1194,7 @@ static itpp_status run_gates_on(itpp_ctx c, double dtau, int64_t n_gates, itpp_s
       c->fwd_gates += idx;
       nospec_next = true;
       ++retries;
+      c->short_batches = kShortBatchesAfterHalt;
       continue;
     }
     done += batch;
