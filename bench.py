@@ -318,7 +318,8 @@ def run_form_batched(args):
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     b = P.batch_for(ws)
-    shape, workers, grid_div, rate = b.autotune(dts, 300, 150)
+    progress("autotune: shape pairs, then workers, then grid divisor (200 warm + 100 timed gates per probe)")
+    shape, workers, grid_div, rate = b.autotune(dts, 200, 100)
     progress(f"autotune: shapes {shape % 3} (n <= 64) and {shape // 3} (n > 64), workers {workers}, "
              f"grid divisor {grid_div}, probe rate {rate:.3e}")
     for _ in range(args.warmup):

@@ -35,6 +35,19 @@ __global__ void init_kernel(Side s0, Plan* plan, Filter* filt, Ctl* ctl, int w0)
   *ctl = c;
 }
 
+// This lane's slot among the active lanes of its wave that pass `want`,
+// reserved with one LDS atomic per wave on *counter.
+__device__ __forceinline__ uint32_t wave_claim(bool want, uint32_t* counter) {
+  const uint64_t act = __ballot(1);
+  const uint64_t m = __ballot(want);
+  const int lane = (int)(threadIdx.x & 63u);
+  const int leader = __ffsll((unsigned long long)act) - 1;
+  uint32_t base = 0;
+  if (lane == leader && m) base = atomicAdd(counter, (uint32_t)__popcll(m));
+  base = __shfl(base, leader, 64);
+  return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+}
+
 // Parallel search, over a histogram of nbins bins taken from the top,
 // for the bin where the running count from above first reaches `need`
 // (counts above the histogram: `base`).  Returns the bin (or -1) and the
@@ -322,6 +335,31 @@ __global__ void select_collect(Side out, const Plan* plan, Ctl* ctl, SelBuf sel)
     }
 }
 
+// Canonical form of a rep key through the inverse bit map inv (rep position
+// -> canonical bit, in LDS), visiting only the set bits: the strings of a tie
+// group are mostly of low weight, so this is far cheaper than walking all
+// 2n canonical bits.
+template <int NW>
+__device__ __forceinline__ Key<NW> canonical_sparse(const Key<NW>& k, const uint16_t* inv, int n) {
+  constexpr int W = NW / 2;
+  Key<NW> c;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) c.w[i] = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    uint64_t w = k.w[i];
+    while (w) {
+      const int b = __ffsll((unsigned long long)w) - 1;
+      w &= w - 1ull;
+      const int cb = inv[64 * i + b];
+      const int word = cb < n ? (cb >> 6) : (W + ((cb - n) >> 6));
+      const int bit = cb < n ? (cb & 63) : ((cb - n) & 63);
+      xor_bit(c, 64 * word + bit, 1ull);
+    }
+  }
+  return c;
+}
+
 // Exact K-th value among the candidates (radix select on the |c| bits) and,
 // for ties at that value, the largest canonical key still kept.
 template <int NW>
@@ -332,7 +370,7 @@ __global__ __launch_bounds__(1024) void select_exact(Side out, const Filter* fil
   __shared__ int s_bin;
   __shared__ uint64_t s_above;
   __shared__ uint32_t s_cnt0;
-  __shared__ unsigned long long s_ntie;
+  __shared__ uint32_t s_ntie;
   // candidates left after the first radix pass, when few enough (bits, index)
   constexpr uint32_t kLdsCand = 4096;
   // tie sets up to this size are ranked directly (their keys fill lb)
@@ -419,46 +457,72 @@ __global__ __launch_bounds__(1024) void select_exact(Side out, const Filter* fil
   __syncthreads();
   if (count_eq <= need_eq) return;
   // ties: gather canonical keys of the elements equal to kth
+  __shared__ uint16_t inv[kMaxBits];
+  for (int cb = tid; cb < rp.nbits; cb += blockDim.x) inv[rp.pos[cb]] = (uint16_t)cb;
+  __syncthreads();
   const uint64_t mt = in_lds ? nl : m;
   for (uint64_t i = tid; i < mt; i += blockDim.x) {
-    if ((in_lds ? lb[i] : sel.cand_bits[i]) != kth) continue;
+    const bool tie = (in_lds ? lb[i] : sel.cand_bits[i]) == kth;
+    // one LDS atomic per wave, not per tied element (tie groups can hold
+    // hundreds of thousands of strings)
+    const uint32_t slot = wave_claim(tie, &s_ntie);
+    if (!tie) continue;
     Key<NW> k = load_key<NW>(out, sel.cand_idx[in_lds ? li[i] : i]);
-    Key<NW> ck = to_canonical(k, rp.pos, rp.nbits);
-    const unsigned long long slot = atomicAdd(&s_ntie, 1ull);
-    for (int q = 0; q < NW; ++q) sel.tie_keys[slot * NW + q] = ck.w[q];
+    Key<NW> ck = canonical_sparse(k, inv, rp.nbits / 2);
+    for (int q = 0; q < NW; ++q) sel.tie_keys[(uint64_t)slot * NW + q] = ck.w[q];
   }
   __syncthreads();
   const uint64_t nt = s_ntie;
-  if (nt <= kTieDirect) {
-    // few ties: the tied keys are distinct strings, so the kept one with the
-    // largest canonical key is the one with exactly need_eq - 1 keys below it
-    uint64_t* tk = lb;  // the candidate list is no longer needed
-    for (uint64_t i = tid; i < nt; i += blockDim.x)
-      for (int q = 0; q < NW; ++q) tk[q * kTieDirect + i] = sel.tie_keys[i * NW + q];
+  // The kept tied key is the needk-th smallest canonical key of the tied
+  // keys matching (pre, msk) (they are distinct strings).  Once at most
+  // kTieDirect keys match, they are ranked directly in LDS: the one with
+  // exactly needk - 1 keys below it.
+  uint64_t* tk = lb;  // the candidate list is no longer needed
+  __shared__ uint32_t s_nd;
+  auto rank_direct = [&](const uint64_t* keys, uint64_t nk, const Key<NW>& pre, const Key<NW>& msk,
+                         uint64_t needk) {
+    if (tid == 0) s_nd = 0;
     __syncthreads();
-    for (uint64_t i = tid; i < nt; i += blockDim.x) {
+    for (uint64_t i = tid; i < nk; i += blockDim.x) {
+      bool match = true;
+      for (int q = 0; q < NW; ++q) match = match && ((keys[i * NW + q] & msk.w[q]) == pre.w[q]);
+      const uint32_t slot = wave_claim(match, &s_nd);
+      if (match)
+        for (int q = 0; q < NW; ++q) tk[q * kTieDirect + slot] = keys[i * NW + q];
+    }
+    __syncthreads();
+    const uint32_t nd = s_nd;
+    for (uint32_t i = tid; i < nd; i += blockDim.x) {
       Key<NW> ki;
       for (int q = 0; q < NW; ++q) ki.w[q] = tk[q * kTieDirect + i];
       uint32_t below = 0;
-      for (uint64_t j2 = 0; j2 < nt; ++j2) {
+      for (uint32_t j2 = 0; j2 < nd; ++j2) {
         Key<NW> kj;
         for (int q = 0; q < NW; ++q) kj.w[q] = tk[q * kTieDirect + j2];
         below += (j2 != i && canon_le(kj, ki)) ? 1u : 0u;
       }
-      if (below + 1u == need_eq) {
+      if ((uint64_t)below + 1u == needk) {
         filt_out->tie_active = 1;
         for (int q = 0; q < NW; ++q) filt_out->tie_key[q] = ki.w[q];
       }
     }
+  };
+  Key<NW> pre, msk;
+  for (int q = 0; q < NW; ++q) pre.w[q] = msk.w[q] = 0;
+  if (nt <= kTieDirect) {
+    rank_direct(sel.tie_keys, nt, pre, msk, need_eq);
     return;
   }
+  // the keys still matching the prefix, compacted after every pass into the
+  // candidate arrays (free now), which hold sel.cap words each
+  const uint64_t* keys = sel.tie_keys;
+  uint64_t nk = nt;
+  __shared__ uint32_t s_nc;
   // MSB-first radix selection (8-bit digits, X words before Z words) of
-  // the need_eq-th smallest canonical key
+  // the need_eq-th smallest canonical key, until few enough keys match
   constexpr int W = NW / 2;
   const int n = rp.nbits / 2;
   const int ndig = (n + 7) / 8;  // digits per part; bits above n are zero in every key
-  Key<NW> pre, msk;
-  for (int q = 0; q < NW; ++q) pre.w[q] = msk.w[q] = 0;
   uint64_t needk = need_eq;
   for (int part = 0; part < 2; ++part) {
     for (int d = ndig - 1; d >= 0; --d) {
@@ -472,11 +536,11 @@ __global__ __launch_bounds__(1024) void select_exact(Side out, const Filter* fil
       }
       __syncthreads();
       uint32_t local = 0;
-      for (uint64_t i = tid; i < nt; i += blockDim.x) {
+      for (uint64_t i = tid; i < nk; i += blockDim.x) {
         bool match = true;
-        for (int q = 0; q < NW; ++q) match = match && ((sel.tie_keys[i * NW + q] & msk.w[q]) == pre.w[q]);
+        for (int q = 0; q < NW; ++q) match = match && ((keys[i * NW + q] & msk.w[q]) == pre.w[q]);
         if (match) {
-          atomicAdd(&h[(sel.tie_keys[i * NW + word] >> sh) & 0xffull], 1u);
+          atomicAdd(&h[(keys[i * NW + word] >> sh) & 0xffull], 1u);
           ++local;
         }
       }
@@ -490,7 +554,27 @@ __global__ __launch_bounds__(1024) void select_exact(Side out, const Filter* fil
       needk -= below;
       pre.w[word] |= (uint64_t)bsel << sh;
       msk.w[word] |= 0xffull << sh;
+      const uint32_t left = h[bsel];
       __syncthreads();
+      if (left <= kTieDirect) {
+        rank_direct(keys, nk, pre, msk, needk);
+        return;
+      }
+      if ((uint64_t)left * NW <= sel.cap && left < nk) {
+        uint64_t* dst = keys == sel.cand_bits ? sel.cand_idx : sel.cand_bits;
+        if (tid == 0) s_nc = 0;
+        __syncthreads();
+        for (uint64_t i = tid; i < nk; i += blockDim.x) {
+          bool match = true;
+          for (int q = 0; q < NW; ++q) match = match && ((keys[i * NW + q] & msk.w[q]) == pre.w[q]);
+          const uint32_t slot = wave_claim(match, &s_nc);
+          if (match)
+            for (int q = 0; q < NW; ++q) dst[(uint64_t)slot * NW + q] = keys[i * NW + q];
+        }
+        __syncthreads();
+        keys = dst;
+        nk = left;
+      }
     }
   }
   if (tid == 0) {
