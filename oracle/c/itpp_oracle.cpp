@@ -82,6 +82,13 @@ struct Oracle {
   double term_updates = 0.0;
   long long gates = 0;
   int max_weight = 0;  // 0: no weight cutoff
+  // Alternative readings of where the threshold applies, for the paper's
+  // threshold-sweep counts (not Algorithm 1; only with no cap binding):
+  // 1 = threshold once per Trotter step, on the normalised state after its
+  //     last gate (the gates of a step only propagate and normalise);
+  // 2 = threshold every contribution of Eq. ITPP_PropRules before the
+  //     accumulation, then the sums as in Algorithm 1.
+  int reading = 0;
 };
 
 int pauli_weight(const std::string& P) {
@@ -136,7 +143,7 @@ int one_gate(Oracle* o, std::unordered_map<std::string, T>& S, const std::string
       if (a != 'I' && a != b) ++anti;
     }
     if (anti % 2) {
-      out[P] += c;
+      if (o->reading != 2 || (double)std::fabs(c) > delta) out[P] += c;
       continue;
     }
     std::string R = P;
@@ -152,8 +159,9 @@ int one_gate(Oracle* o, std::unordered_map<std::string, T>& S, const std::string
       return 2;
     }
     const T sign = (k == 0) ? (T)1 : (T)-1;
-    out[P] += (T)(ch * c);
-    out[R] += (T)((T)(-sh * sign) * c);
+    const T vs = (T)(ch * c), vb = (T)((T)(-sh * sign) * c);
+    if (o->reading != 2 || (double)std::fabs(vs) > delta) out[P] += vs;
+    if (o->reading != 2 || (double)std::fabs(vb) > delta) out[R] += vb;
   }
   // truncate: threshold
   std::vector<std::pair<std::string, T>> kept;
@@ -222,13 +230,24 @@ int evolve_impl(Oracle* o, int n_terms, const char* strings, const double* alpha
   const std::string ident(n, 'I');
   std::vector<std::string> terms(n_terms);
   for (int k = 0; k < n_terms; ++k) terms[k] = std::string(strings + (size_t)k * n, n);
+  const bool per_step = o->reading == 1;
   for (long long step = 0; step < n_steps; ++step) {
     for (int g = 0; g < n_gates; ++g) {
       const std::string& Q = terms[term_idx[g]];
       if (Q == ident) continue;
       const double theta = alpha[term_idx[g]] * mult[g] * dtau;
-      const int rc = one_gate<T>(o, S, Q, theta, delta, K, nullptr);
+      const int rc = one_gate<T>(o, S, Q, theta, per_step ? -1.0 : delta, per_step ? (long long)1 << 62 : K, nullptr);
       if (rc) return rc;
+    }
+    if (per_step) {
+      for (auto it = S.begin(); it != S.end();) {
+        if (it->first != ident && !((double)std::fabs(it->second) > delta)) it = S.erase(it);
+        else ++it;
+      }
+      if ((long long)S.size() > K) {
+        o->err = "the per-step threshold reading runs without a binding cap";
+        return 3;
+      }
     }
   }
   return 0;
@@ -403,6 +422,9 @@ void* itpp_oracle_new32(int n) {
 }
 
 void itpp_oracle_free(void* h) { delete static_cast<Oracle*>(h); }
+
+// Threshold reading of the following runs (0: Algorithm 1; 1 and 2: see Oracle::reading).
+void itpp_oracle_set_reading(void* h, int reading) { static_cast<Oracle*>(h)->reading = reading; }
 
 // Pauli-weight cutoff for the following gates (0: none).
 void itpp_oracle_set_max_weight(void* h, int max_weight) { static_cast<Oracle*>(h)->max_weight = max_weight; }

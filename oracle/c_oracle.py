@@ -43,6 +43,8 @@ def _load():
                                            ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_double, ctypes.c_longlong,
                                            ctypes.c_double, ctypes.c_longlong]
+        lib.itpp_oracle_set_reading.restype = None
+        lib.itpp_oracle_set_reading.argtypes = [ctypes.c_void_p, ctypes.c_int]
         lib.itpp_oracle_set_max_weight.restype = None
         lib.itpp_oracle_set_max_weight.argtypes = [ctypes.c_void_p, ctypes.c_int]
         lib.itpp_oracle_size.restype = ctypes.c_longlong
@@ -92,6 +94,11 @@ class COracle:
                                           int(n_steps), float(delta), int(K))
         if rc != 0:
             raise RuntimeError(self._lib.itpp_oracle_error(self._h).decode())
+
+    def set_reading(self, reading: int) -> None:
+        """Where the threshold applies: 0 Algorithm 1 (after every gate),
+        1 once per Trotter step, 2 on every contribution before the sums."""
+        self._lib.itpp_oracle_set_reading(self._h, int(reading))
 
     def set_max_weight(self, max_weight: int) -> None:
         """Pauli-weight cutoff of the following gates (0: none)."""

@@ -68,7 +68,7 @@ def main():
     sweep_table("Thermal state, N = 12, beta = 3", n, 3.0, eth, ks)
 
     K = 2704156
-    ns = [12, 20, 28, 36, 44] if args.quick else list(range(12, 50, 4))
+    ns = [12, 20, 28, 36, 44] if args.quick else list(range(12, 52, 2))
     print(f"\n### Fixed cap K = {K}, tau = 20\n")
     print("| N | energy per site | exact | relative error | cap reached | seconds |")
     print("|---:|---:|---:|---:|---|---:|")

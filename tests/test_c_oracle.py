@@ -143,3 +143,24 @@ def test_word_import_export_roundtrip(n):
     # the same multiset as the input
     order = np.lexsort(tuple(z[:, q] for q in range(x.shape[1])) + tuple(x[:, q] for q in range(x.shape[1])))
     assert np.array_equal(x[order], x2) and np.array_equal(z[order], z2) and np.array_equal(c[order], c2)
+
+
+def test_threshold_readings_reduce_to_algorithm_1_without_truncation():
+    """The oracle's alternative threshold readings (once per Trotter step;
+    every contribution before the sums) equal Algorithm 1 when the threshold
+    truncates nothing, and differ from it when it does."""
+    c_oracle.build(force=False)
+    w = W.tfim_workload("t", 8, 1.0, 0.5, False, 1, 0.04, 0.4, 1e-300, 10 ** 9)
+    ref = c_oracle.run_workload(w).state()
+    for reading in (1, 2):
+        o = c_oracle.COracle(w.n)
+        o.set_reading(reading)
+        o.evolve(w.strings, w.alphas, w.schedule, w.dtau, w.n_steps, w.delta, w.K)
+        assert o.state() == ref
+    states = []
+    for reading in (0, 1, 2):
+        o = c_oracle.COracle(w.n)
+        o.set_reading(reading)
+        o.evolve(w.strings, w.alphas, w.schedule, w.dtau, w.n_steps, 2.0 ** -7, w.K)
+        states.append(o.state())
+    assert states[0] != states[1] and states[0] != states[2]
