@@ -1115,7 +1115,9 @@ static itpp_status run_gates_on(itpp_ctx c, double dtau, int64_t n_gates, itpp_s
     const int64_t span = can_graph ? (G - c->gpos) % G + std::max<int64_t>(1, kSyncEvery / GR) * GR : kSyncEvery;
     int64_t batch = std::min<int64_t>(n_gates - done, span);
     if (c->short_batches > 0) {
-      batch = std::min<int64_t>(batch, kSyncAfterHalt);
+      // with step graphs a short batch still holds one whole recorded step
+      const int64_t lim = can_graph ? (G - c->gpos) % G + GR : kSyncAfterHalt;
+      batch = std::min<int64_t>(batch, lim);
       --c->short_batches;
     }
     if (E > 0 && c->fwd_valid) {
