@@ -23,6 +23,7 @@
 // partner gives fl(fl(ch*c) + fl(-+sh*c')), without partner fl(ch*c) and a
 // branch -+fl(sh*c); an anticommuting string keeps c.  Inputs are normalised
 // on load with an IEEE division by the previous identity coefficient.
+#include <type_traits>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -434,8 +435,11 @@ __global__ __launch_bounds__(BLOCK, 4) void gate_kernel(GateParams gp, Side in, 
     while (j + 1 < sm.L.njoin && t >= sm.L.tiles_before[j + 1]) ++j;
     const uint64_t tl = t - sm.L.tiles_before[j];
     const int cA = j, cB = j ^ full;
-    const ClassView VA = sm.L.views[cA];
-    const ClassView VB = sm.L.views[cB];
+    // the reverse kernel reads the class views from LDS where it needs them
+    // (kept in registers they make it spill); the forward kernel copies them
+    using ViewT = std::conditional_t<ADJ, const ClassView&, const ClassView>;
+    ViewT VA = sm.L.views[cA];
+    ViewT VB = sm.L.views[cB];
     (void)tl;
     const uint64_t i0 = sm.pf[0], j0 = sm.pf[1];
     const int nAt = (int)(sm.pf[2] - i0);
