@@ -401,6 +401,18 @@ def run_form_adjoint(args):
     zz = sum(e.expect([w.strings[k]], [1.0]) for k in range(nzz))
     xx = sum(e.expect([w.strings[k]], [1.0]) for k in range(nzz, 2 * nzz))
     e.close()
+    # the same sweep with checkpoints every step: each segment's states fit
+    # in device memory, so every segment is recomputed once instead of twice
+    e = P.engine_for(w)
+    e.set_adjoint(1)
+    e.evolve(w.dtau, w.n_steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L1, _, dd1, _ = e.backward(*H)
+    torch.cuda.synchronize()
+    t_bwd1 = time.perf_counter() - t0
+    e.close()
+    progress(f"reverse sweep, checkpoints every step {t_bwd1:.2f} s")
     beta = w.dtau * w.n_steps
     dE_dJ = -zz - float(sum(da[:nzz]))
     dE_dh = -xx - float(sum(da[nzz:]))
@@ -412,7 +424,9 @@ def run_form_adjoint(args):
     line["form"] = {"plain_forward_s": t_fwd, "plain_forward_value": st["term_updates"] / t_fwd,
                     "checkpointed_forward_s": t_fwd_ck, "reverse_sweep_s": t_bwd,
                     "backward_over_forward": t_bwd / t_fwd, "energy": L, "energy_plain_forward": E_plain,
-                    "dE_dJ": dE_dJ, "dE_dh": dE_dh, "dE_dbeta": dE_db, "specific_heat": -beta * beta * dE_db}
+                    "dE_dJ": dE_dJ, "dE_dh": dE_dh, "dE_dbeta": dE_db, "specific_heat": -beta * beta * dE_db,
+                    "reverse_sweep_every_step_s": t_bwd1, "backward_over_forward_every_step": t_bwd1 / t_fwd,
+                    "every_step_same_result": L1 == L and dd1 == dd}
     return line, w
 
 

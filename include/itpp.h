@@ -266,8 +266,10 @@ itpp_status itpp_set_adjoint(itpp_ctx ctx, int32_t every_steps, int64_t workspac
  * (nothing written) when that is fewer than the gates (itpp_num_gates).
  * Requires a forward run since then with itpp_set_adjoint enabled, one dtau
  * and imaginary-time gates only (ITPP_ERR_STATE otherwise).  Between the stored copies the states are
- * recomputed (sub-checkpoints every ~sqrt(segment) gates); ITPP_ERR_OOM if
- * the workspace cannot hold them.  The current state is the same after the
+ * recomputed: once, when every state of a segment fits in the workspace
+ * (each at most 2 * max_terms + 1 strings), else twice, with sub-checkpoints
+ * every ~sqrt(segment) gates; ITPP_ERR_OOM if the workspace cannot hold
+ * those.  The current state is the same after the
  * call; after an error it needs a reset. */
 itpp_status itpp_backward(itpp_ctx ctx, int32_t n_strings, const uint64_t* x, const uint64_t* z,
                           const double* coef, double* value, double* d_alpha, double* d_dtau, double* d_theta,

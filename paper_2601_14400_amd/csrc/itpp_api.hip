@@ -1711,27 +1711,35 @@ itpp_status backward_impl(itpp_ctx c, int32_t m, const uint64_t* dx, const uint6
     const int64_t b = (k + 1 < nck) ? c->ckpts[k + 1].gate : Gtot;
     if (b <= a) continue;
     const int64_t L = b - a;
-    int64_t sblk = (int64_t)std::ceil(std::sqrt((double)L));
-    if (sblk < 1) sblk = 1;
     ar.top = keep_top;
-    // sub-checkpoints every sblk gates of the segment
+    // Every state of the segment fits in the workspace (a stored state holds
+    // at most two outputs per survivor, 2K + 1 strings): one block, recomputed
+    // once.  Otherwise blocks of about sqrt(L) gates from sub-checkpoints of a
+    // first recomputation, so the segment is recomputed twice.
+    const uint64_t snap_max = snapshot_bytes(c, 2 * (uint64_t)c->cfg.max_terms + 64) + 256;
+    const bool whole = ar.size - ar.top >= (uint64_t)(L + 1) * snap_max;
+    int64_t sblk = whole ? L : (int64_t)std::ceil(std::sqrt((double)L));
+    if (sblk < 1) sblk = 1;
     std::vector<Snapshot> subs;
     Snapshot s0 = c->ckpts[k];
     s0.owned = nullptr;
     subs.push_back(s0);
-    HIP_TRY(c, restore_snapshot(c, c->ckpts[k]));
-    for (int64_t g = a; g < b - 1; ++g) {
-      st = replay_gate(c);
-      if (st != ITPP_OK) return st;
-      if ((c->fwd_gates - a) % sblk == 0) {
-        Snapshot sn;
-        st = snap_in_arena(c, ar, sn);
+    if (!whole) {
+      // sub-checkpoints every sblk gates of the segment
+      HIP_TRY(c, restore_snapshot(c, c->ckpts[k]));
+      for (int64_t g = a; g < b - 1; ++g) {
+        st = replay_gate(c);
         if (st != ITPP_OK) return st;
-        subs.push_back(sn);
+        if ((c->fwd_gates - a) % sblk == 0) {
+          Snapshot sn;
+          st = snap_in_arena(c, ar, sn);
+          if (st != ITPP_OK) return st;
+          subs.push_back(sn);
+        }
       }
+      st = check_error(c);
+      if (st != ITPP_OK) return st;
     }
-    st = check_error(c);
-    if (st != ITPP_OK) return st;
     const uint64_t sub_top = ar.top;
     const int64_t nblk = (L + sblk - 1) / sblk;
     for (int64_t q = nblk - 1; q >= 0; --q) {

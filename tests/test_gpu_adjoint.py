@@ -95,11 +95,18 @@ def test_reverse_sweep_many_tiles_matches_oracle(n, K):
 
 
 def test_checkpoint_interval_does_not_change_results():
+    """Checkpoint intervals and workspace sizes change only what is
+    recomputed: with the default workspace every segment's states fit and
+    each segment is recomputed once; a 2 MB workspace forces blocks of about
+    sqrt(L) gates from sub-checkpoints (two recomputations)."""
     w = W.tfim_workload("t", 20, 1.0, 1.1, True, 1, 0.05, 0.3, 1e-6, 500)
     obs = (w.strings, w.alphas)
     ref = None
-    for every in (1, 2, 5, 100):
-        e, st, out = gpu_backward(w, obs, 5, every)
+    for every, ws in ((1, 0), (2, 0), (5, 0), (100, 0), (5, 2 << 20), (100, 2 << 20)):
+        e = P.engine_for(w)
+        e.set_adjoint(every, ws)
+        e.evolve(w.dtau, 5)
+        out = e.backward(*obs, want_theta=True)
         e.close()
         if ref is None:
             ref = out
