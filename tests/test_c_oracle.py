@@ -2,6 +2,7 @@
 and is pinned on its own to a closed form at a size the Python oracle does
 not reach quickly.  CPU only."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -164,3 +165,26 @@ def test_threshold_readings_reduce_to_algorithm_1_without_truncation():
         o.evolve(w.strings, w.alphas, w.schedule, w.dtau, w.n_steps, 2.0 ** -7, w.K)
         states.append(o.state())
     assert states[0] != states[1] and states[0] != states[2]
+
+
+def test_sanitized_build_runs_clean(tmp_path):
+    """The C++ oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (g++, host code only) runs every entry point on a small capped chain
+    without a report (oracle/c/sanitize_main.cpp)."""
+    import shutil
+    import subprocess
+
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    here = os.path.dirname(c_oracle.SRC)
+    exe = str(tmp_path / "oracle_san")
+    cmd = [gxx, "-O1", "-g", "-std=c++17", "-fno-omit-frame-pointer", "-ffp-contract=off",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+           c_oracle.SRC, os.path.join(here, "sanitize_main.cpp"), "-o", exe]
+    subprocess.check_call(cmd)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:verify_asan_link_order=0", UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "0 failures" in r.stdout
+    assert "runtime error" not in r.stderr and "ERROR: AddressSanitizer" not in r.stderr
