@@ -255,10 +255,37 @@ class Engine:
         x, z = strings_to_words(keys, self.n)
         self.import_words(x, z, np.array([S[k] for k in keys], dtype=np.float64))
 
-    def evolve(self, dtau: float, n_steps: int) -> Dict[str, float]:
-        st = ItppStats()
-        self._check(self._lib.itpp_evolve(self._h, float(dtau), int(n_steps), ctypes.byref(st)))
-        return self._stats(st)
+    def evolve(self, dtau: float, n_steps: int, log: Optional[List[Dict[str, float]]] = None) -> Dict[str, float]:
+        """n_steps Trotter steps of dtau; returns the call's statistics.  With
+        ``log`` (a list) the steps run one call each and every step's
+        statistics are appended to it (a per-step metrics log: strings kept,
+        c_I, whether the cap bound, the smallest K-th magnitude, redone
+        gates, ...); the summed statistics are returned as without it."""
+        if log is None:
+            st = ItppStats()
+            self._check(self._lib.itpp_evolve(self._h, float(dtau), int(n_steps), ctypes.byref(st)))
+            return self._stats(st)
+        tot: Optional[Dict[str, float]] = None
+        for _ in range(int(n_steps)):
+            st = ItppStats()
+            self._check(self._lib.itpp_evolve(self._h, float(dtau), 1, ctypes.byref(st)))
+            d = self._stats(st)
+            log.append(d)
+            if tot is None:
+                tot = dict(d)
+            else:
+                for k in ("n_gates", "term_updates", "alg_bytes", "spec_gates", "spec_retries", "written",
+                          "graph_steps"):
+                    tot[k] += d[k]
+                for k in ("n_terms", "c_identity"):
+                    tot[k] = d[k]
+                tot["cap_hit"] = max(tot["cap_hit"], d["cap_hit"])
+                tot["c_I_min"] = min(tot["c_I_min"], d["c_I_min"])
+                tot["c_I_max"] = max(tot["c_I_max"], d["c_I_max"])
+                tot["kth_abs_min"] = min(tot["kth_abs_min"], d["kth_abs_min"])
+        if tot is None:
+            return self.evolve(dtau, 0)
+        return tot
 
     def evolve_gates(self, dtau: float, n_gates: int) -> Dict[str, float]:
         st = ItppStats()

@@ -273,3 +273,24 @@ def test_speculation_never_changes_results(margin):
         e.close()
     o = c_oracle.run_workload(w, n_steps=3)
     assert_same_state(o.state(), ref)
+
+
+def test_per_step_metrics_log():
+    """evolve(..., log=[]) runs the same steps one call each and records
+    every step's statistics; the state and the summed statistics equal one
+    call's."""
+    w = W.config2(K=3000)
+    e = P.engine_for(w)
+    log = []
+    tot = e.evolve(w.dtau, 5, log=log)
+    S = e.state()
+    e.close()
+    e2 = P.engine_for(w)
+    ref = e2.evolve(w.dtau, 5)
+    S2 = e2.state()
+    e2.close()
+    assert S == S2 and len(log) == 5
+    assert tot["term_updates"] == ref["term_updates"] and tot["n_gates"] == ref["n_gates"] == 5 * 190
+    assert tot["n_terms"] == ref["n_terms"] == log[-1]["n_terms"]
+    assert sum(d["term_updates"] for d in log) == ref["term_updates"]
+    assert [d["n_gates"] for d in log] == [190] * 5
