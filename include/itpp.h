@@ -98,8 +98,10 @@ typedef struct {
   double c_I_max;        /*   over the gates (Sec. II.C normalisation) */
   double kth_abs_min;    /* smallest K-th largest |c| (normalised) over the gates whose cap
                             bound (K-truncation, Sec. II.C); +inf if none */
-  int64_t graph_steps;   /* Trotter steps of this call run as replays of a recorded
-                            step graph (ITPP_OPT_GRAPHS) */
+  int64_t graph_steps;   /* Trotter steps of this call launched as replays of a
+                            recorded step graph (ITPP_OPT_GRAPHS); a replay cut short
+                            by a redone speculative gate counts too, so with redos
+                            this can exceed the steps of the call */
 } itpp_stats;
 
 /* Kernel timing gathered with HIP events on the context's stream while
