@@ -103,6 +103,43 @@ def test_untruncated_2d_lattice_equals_trotterized_dense(Lx, Ly, periodic, order
     assert _coef_err(S, A) < 1e-12
 
 
+def xxz_chain(n, jxy, jz, periodic):
+    """XX, YY and ZZ on every bond (YY flips four key bits: the GPU path
+    rejects it, the oracle takes any string)."""
+    bonds = [(i, i + 1) for i in range(n - 1)] + ([(n - 1, 0)] if periodic and n > 2 else [])
+    strings, alphas = [], []
+    for letter, a in (("X", jxy), ("Y", jxy), ("Z", jz)):
+        for i, j in bonds:
+            s = ["I"] * n
+            s[i] = s[j] = letter
+            strings.append("".join(s))
+            alphas.append(a)
+    return strings, alphas, len(bonds)
+
+
+@pytest.mark.parametrize("n,periodic,order,jz", [(4, False, 1, 0.6), (5, True, 2, 1.0), (6, False, 2, -0.4)])
+def test_untruncated_xxz_chain_equals_trotterized_dense(n, periodic, order, jz):
+    """XXZ and Heisenberg chains: without truncation the oracle reproduces
+    Eq. ThermalTrotter for terms with Y letters on two sites; the Strang
+    split halves the XX and YY groups around the ZZ group."""
+    strings, alphas, nb = xxz_chain(n, 1.0, jz, periodic)
+    xx, yy, zz = range(0, nb), range(nb, 2 * nb), range(2 * nb, 3 * nb)
+    if order == 1:
+        sched = [(k, 1.0) for k in range(3 * nb)]
+    else:
+        sched = ([(k, 0.5) for k in xx] + [(k, 0.5) for k in yy] + [(k, 1.0) for k in zz]
+                 + [(k, 0.5) for k in yy] + [(k, 0.5) for k in xx])
+    dtau, steps = 0.05, 8
+    S, _ = itpp.evolve(n, strings, alphas, sched, dtau, steps, 0.0, 1 << 40)
+    rho = dense.trotter_thermal(strings, alphas, sched, dtau, steps)
+    A = dense.pauli_coefficients(rho, tol=1e-14)
+    assert _coef_err(S, A) < 1e-12
+    assert any("Y" in k for k in S)
+    # the Trotter product commutes with the global flips (each term does)
+    for P in S:
+        assert sum(ch in "XY" for ch in P) % 2 == 0 and sum(ch in "ZY" for ch in P) % 2 == 0
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_untruncated_random_hamiltonian_with_y_terms(seed):
     w = W.random_workload("r", 4, 7, seed, 0.1, 4, 0.0, 1 << 40, max_weight=3, local=False)
