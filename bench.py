@@ -50,6 +50,13 @@ TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "gate_kernel_traffic_tfim_n64_op
 COPY_BYTES = 256 << 20
 
 
+
+# Every form but the small state runs the 512-thread gate kernel (gate shape
+# 1) at every state size: it is the kernel their roofline and rocprofv3
+# summaries cover.  The library's automatic default would run gates on states
+# of at most 2^19 strings on the layer kernel instead (faster there).
+GATE_SHAPE = 1
+
 def kernel_source_hash() -> str:
     import hashlib
 
@@ -204,6 +211,7 @@ def run_form_fp32(args):
     for prec in ("f32", "f64"):
         w = W.config3(K=K, beta=args.beta if args.beta != 2.0 else 1.0, precision=prec)
         eng = P.engine_for(w)
+        eng.set_option("gate_shape", GATE_SHAPE)
         obs = w.observables
         for _ in range(args.warmup):
             eng.reset()
@@ -316,6 +324,7 @@ def run_form_batched(args):
     tu_seq = 0.0
     for i, w in enumerate(ws):
         e = P.engine_for(w)
+        e.set_option("gate_shape", GATE_SHAPE)
         tu_seq += e.evolve(w.dtau, w.n_steps)["term_updates"]
         e.close()
         if i % 8 == 7:
@@ -374,6 +383,7 @@ def run_form_adjoint(args):
     H = (w.strings, w.alphas)
     # plain forward
     e = P.engine_for(w)
+    e.set_option("gate_shape", GATE_SHAPE)
     e.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -441,6 +451,7 @@ def run_form_squared(args):
     K = 1 << 20
     w = W.config2(K=K)
     e = P.engine_for(w)
+    e.set_option("gate_shape", GATE_SHAPE)
     st = e.evolve(w.dtau, w.n_steps)
     torch.cuda.synchronize()
     N = st["n_terms"]
@@ -489,6 +500,7 @@ def run_form_realtime(args):
                                       step=19.5 / (1 << 20))
     progress("synthetic state generated")
     e = P.engine_for(w)
+    e.set_option("gate_shape", GATE_SHAPE)
     e.import_words(x, z, c)
     e.set_option("real_time", 1)
     e.evolve(w.dtau, 1)  # warm-up: one step, so every schedule position has its K-th value ratio
@@ -593,6 +605,7 @@ def main():
     torch.cuda.set_device(0)
     w = W.config2(K=args.K, beta=args.beta)
     eng = P.engine_for(w)
+    eng.set_option("gate_shape", GATE_SHAPE)
     obs = w.observables
 
     def one_step():
@@ -657,7 +670,7 @@ def main():
         "config": {"workload": f"tfim_n{w.n}_open_strang_dtau{w.dtau}_beta{args.beta}_delta1e-6_K{args.K}",
                    "n_qubits": w.n, "K": args.K, "delta": w.delta, "dtau": w.dtau,
                    "trotter_steps": w.n_steps, "gates_per_step": st["n_gates"],
-                   "h": w.meta["h"], "seed": w.meta["seed"]},
+                   "h": w.meta["h"], "seed": w.meta["seed"], "gate_shape": GATE_SHAPE},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "gate_kernel", "avg_launch_ms": avg_ms,

@@ -287,10 +287,15 @@ itpp_status itpp_num_gates(itpp_ctx ctx, int64_t* out);
  *    previous gate; if fewer than K-1 strings pass, the gate is redone
  *    without the margin, so the kept set is always the exact one.
  *  ITPP_OPT_SPEC_MARGIN (default 0.98): that margin as a factor in (0, 1].
- *  ITPP_OPT_GATE_SHAPE (default 0 for n <= 64, 1 above): 0 = one 1024-thread workgroup per CU
- *    with 4000 (n <= 64) or 2000 (n <= 128) strings per tile; 1 = two
- *    512-thread workgroups per CU with 2000 or 1500 strings per tile (more
- *    tiles in flight, better for small states).
+ *  ITPP_OPT_GATE_SHAPE (default 3): the gate kernel's launch shape.
+ *    0 = one 1024-thread workgroup per CU with 4000 (n <= 64) or 2000
+ *    (n <= 128) strings per tile; 1 = two 512-thread workgroups per CU with
+ *    2380 or 1500 strings per tile; 2 = the 256-thread layer kernel with
+ *    1022 strings per tile (runs as 1 while a weight cutoff is set); 3 =
+ *    automatic: 2 while the stored state held at most 2^19 strings at the
+ *    host's last synchronisation (every 512 gates), 1 above, and 1 with
+ *    forward checkpoints (itpp_set_adjoint).  Measured on one MI355X, 2 is
+ *    ahead up to 2^18 strings and 1 from 2^20 on.
  * One option changes the method instead:
  *  ITPP_OPT_REAL_TIME (default 0): 1 applies the real-time rule of Sec. II.B
  *    to the following gates, U_Q(theta)^dagger P U_Q(theta) with

@@ -68,7 +68,8 @@ struct itpp_ctx_s {
   itpp_config cfg{};
   int n = 0, W = 1, NW = 2, nbits = 2;
   int f32 = 0, coef_bytes = 8;  // stored coefficient type: binary32 or binary64
-  int shape = 0;                // gate kernel shape (see gate_tile)
+  int shape = 0;                // ITPP_OPT_GATE_SHAPE (0, 1, 2, or kShapeAuto)
+  uint64_t state_hint = 1;      // stored strings at the last host synchronisation (automatic shape)
   // device memory: own allocations, or a slice of a batch arena
   uint8_t* arena = nullptr;
   uint64_t arena_size = 0, arena_top = 0;
@@ -131,6 +132,7 @@ struct itpp_ctx_s {
   std::vector<int> step_pos;         // bit order at the start of the recorded step
   int step_cur = -1, step_par = -1;  // ping-pong slots it starts from
   double step_dtau = 0.0;
+  int step_shape = -1;               // gate kernel shape it was recorded with
   std::vector<HostSnap> step_snaps;  // host state before each of its gates (serial relative)
   std::vector<int> last_step_pos;    // bit order at the start of the previous step
   int64_t graph_steps = 0;           // steps run as graph replays (statistics)
@@ -147,6 +149,13 @@ namespace {
 const char* kVersion = "itpp gfx950 merge-join engine 0.2";
 // Host synchronisation period (gates) for the speculation check.
 constexpr int64_t kSyncEvery = 512;
+// ITPP_OPT_GATE_SHAPE 3 (the default): shape 2, the 256-thread layer kernel,
+// while the stored state holds at most kAutoShapeMaxStrings strings, shape 1
+// above.  Measured on one MI355X (TFIM chains, whole gates per second), the
+// layer kernel is ahead up to 2^18 strings and behind from 2^20 on, for one-
+// and two-word keys alike.
+constexpr int kShapeAuto = 3;
+constexpr uint64_t kAutoShapeMaxStrings = 1ull << 19;
 // After a speculative gate had to be redone, the next few batches are short:
 // a redone gate turns the rest of its batch into launches that return at
 // once, and failures come in runs (when the cap starts to bind).
@@ -413,6 +422,7 @@ itpp_status do_reset(itpp_ctx c) {
   c->cur = 0;
   c->par = 0;
   c->gpos = 0;
+  c->state_hint = 1;
   HIP_TRY(c, launch_init(c->NW, c->f32, c->side[0], c->plan + 0, c->filt + 0, c->ctl, w0, c->stream));
   c->ready = true;
   return ITPP_OK;
@@ -500,9 +510,7 @@ itpp_status create_impl(const itpp_config* cfg, int dev, const hipDeviceProp_t& 
   c->nbits = 2 * c->n;
   c->f32 = cfg->precision == ITPP_F32 ? 1 : 0;
   c->coef_bytes = c->f32 ? 4 : 8;
-  // two-word keys run faster with two 512-thread workgroups per CU (their
-  // larger keys leave fewer registers per thread at 1024 threads)
-  c->shape = 1;
+  c->shape = kShapeAuto;
   c->stream = static_cast<hipStream_t>(cfg->stream);
   c->device = dev;
   c->cus = prop.multiProcessorCount;
@@ -795,6 +803,7 @@ itpp_status itpp_import(itpp_ctx c, int64_t m, const uint64_t* x, const uint64_t
   HIP_TRY(c, hipMemcpyAsync(c->filt + 0, &fl, sizeof(Filter), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->pos.swap(pos);
+  c->state_hint = (uint64_t)N;
   c->fwd_gates = 0;
   c->fwd_dtau = 0.0;
   c->fwd_valid = true;
@@ -941,6 +950,16 @@ static itpp_status build_gate(itpp_ctx c, int i, const std::vector<int>& pos, do
   return ITPP_OK;
 }
 
+// Gate kernel shape of the next launches: the option, or the size rule of
+// kShapeAuto. With forward checkpoints the automatic choice is shape 1, the
+// layout the reverse sweep replays. The layer kernel has no weight cutoff, so
+// such gates run on shape 1.
+static int effective_shape(itpp_ctx c) {
+  int s = c->shape;
+  if (s == kShapeAuto) s = (c->ckpt_every == 0 && c->state_hint <= kAutoShapeMaxStrings) ? 2 : 1;
+  return (s == 2 && c->max_weight > 0) ? 1 : s;
+}
+
 // Plan and enqueue the next elementary gate of the schedule (asynchronous).
 static itpp_status enqueue_gate(itpp_ctx c, double dtau, bool spec) {
   const int G = (int)c->glist.size();
@@ -948,8 +967,7 @@ static itpp_status enqueue_gate(itpp_ctx c, double dtau, bool spec) {
   GateParams gp;
   std::vector<int> pos1;
   RepPos rp;
-  // the layer kernel (shape 2) has no weight cutoff: such gates run on shape 1
-  const int shape = (c->shape == 2 && c->max_weight > 0) ? 1 : c->shape;
+  const int shape = effective_shape(c);
   itpp_status bs = build_gate(c, i, c->pos, dtau, spec, shape, gp, pos1, rp);
   if (bs != ITPP_OK) return bs;
   const int in = c->cur, out = c->cur ^ 1;
@@ -1039,6 +1057,7 @@ static itpp_status record_step(itpp_ctx c, double dtau, bool* ok) {
   c->step_cur = cur0;
   c->step_par = par0;
   c->step_dtau = dtau;
+  c->step_shape = effective_shape(c);
   c->step_snaps = std::move(snaps);
   *ok = true;
   return ITPP_OK;
@@ -1145,7 +1164,7 @@ static itpp_status run_gates_on(itpp_ctx c, double dtau, int64_t n_gates, itpp_s
     for (int64_t b = 0; b < batch;) {
       if (c->gpos == 0 && can_graph && !(b == 0 && nospec_next) && batch - b >= GR) {
         bool have = c->step_exec && c->step_pos == c->pos && c->step_cur == c->cur && c->step_par == c->par &&
-                    c->step_dtau == dtau;
+                    c->step_dtau == dtau && c->step_shape == effective_shape(c);
         // record once the step-start bit order repeats (from the second step)
         if (!have && c->last_step_pos == c->pos) {
           itpp_status s = record_step(c, dtau, &have);
@@ -1177,7 +1196,11 @@ static itpp_status run_gates_on(itpp_ctx c, double dtau, int64_t n_gates, itpp_s
     }
     nospec_next = false;
     Ctl h{};
+    Filter fl{};
     HIP_TRY(c, hipMemcpyAsync(&h, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+    // the state's size, for the automatic gate kernel shape of the next batch
+    if (c->shape == kShapeAuto)
+      HIP_TRY(c, hipMemcpyAsync(&fl, c->filt + c->par, sizeof(Filter), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (h.error) return check_error(c);
     if (h.halt) {
@@ -1199,6 +1222,7 @@ static itpp_status run_gates_on(itpp_ctx c, double dtau, int64_t n_gates, itpp_s
       c->short_batches = kShortBatchesAfterHalt;
       continue;
     }
+    if (c->shape == kShapeAuto) c->state_hint = fl.n_survivors;
     done += batch;
     c->fwd_gates += batch;
   }
@@ -1246,7 +1270,8 @@ itpp_status itpp_set_option(itpp_ctx c, int32_t option, double value) {
       c->spec_mult = value;
       return ITPP_OK;
     case ITPP_OPT_GATE_SHAPE:
-      if (value != 0.0 && value != 1.0 && value != 2.0) return fail(c, ITPP_ERR_ARG, "gate shape must be 0, 1 or 2");
+      if (value != 0.0 && value != 1.0 && value != 2.0 && value != (double)kShapeAuto)
+        return fail(c, ITPP_ERR_ARG, "gate shape must be 0, 1, 2 or 3 (automatic)");
       c->shape = (int)value;
       return ITPP_OK;
     case ITPP_OPT_REAL_TIME:

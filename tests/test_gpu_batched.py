@@ -66,11 +66,27 @@ def test_batch_instance_matches_oracle():
     (lambda: W.random_two_flip_workload("r", 100, 16, 3, 0.1, 2, 1e-12, 5000), 2),
     (lambda: W.config3(K=3000), 1),
 ])
-def test_gate_shape_1_matches_shape_0(builder, steps):
+def test_gate_shapes_agree(builder, steps):
+    """Shapes 0, 1 and 2 and the automatic choice (the default) store the
+    same state."""
     w = builder()
-    a = single_states([w], [steps])[0]
-    b = single_states([w], [steps], gate_shape=1)[0]
-    assert a == b
+    ref = single_states([w], [steps], gate_shape=0)[0]
+    for shape in (1, 2, 3):
+        assert single_states([w], [steps], gate_shape=shape)[0] == ref, shape
+    assert single_states([w], [steps])[0] == ref
+
+
+def test_automatic_shape_across_its_switch():
+    """The automatic shape runs the layer kernel while the state is small
+    and shape 1 once it has passed 2^19 strings (recording the step graph
+    anew); the state matches both fixed shapes bit for bit."""
+    w = W.config2(K=1 << 20)
+    steps = 40
+    print(f"automatic shape n={w.n} K={w.K} steps={steps}", flush=True)
+    auto = single_states([w], [steps])[0]
+    assert len(auto) > (1 << 19)
+    assert single_states([w], [steps], gate_shape=1)[0] == auto
+    assert single_states([w], [steps], gate_shape=2)[0] == auto
 
 
 def test_autotune_then_evolve():
