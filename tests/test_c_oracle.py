@@ -167,6 +167,45 @@ def test_threshold_readings_reduce_to_algorithm_1_without_truncation():
     assert states[0] != states[1] and states[0] != states[2]
 
 
+@pytest.mark.parametrize("n,periodic,order", [(6, False, 1), (6, True, 2), (8, False, 1)])
+def test_threshold_readings_match_their_definitions(n, periodic, order):
+    """Both alternative readings against compositions of the Python oracle's
+    steps, bit for bit, with a threshold that binds:
+    1 = every gate only propagates and normalises, and the normalised state
+        is thresholded once after the last gate of each Trotter step;
+    2 = every contribution of Eq. ITPP_PropRules is thresholded before the
+        sums, then the gate truncates and normalises as in Algorithm 1."""
+    c_oracle.build(force=False)
+    w = W.tfim_workload("t", n, 1.0, 0.5, periodic, order, 0.04, 0.4, 2.0 ** -7, 10 ** 9)
+    ident = "I" * n
+    gates = [(w.strings[k], math.cosh(w.alphas[k] * m * w.dtau), math.sinh(w.alphas[k] * m * w.dtau))
+             for k, m in w.schedule]
+
+    S1 = {ident: 1.0}
+    for _ in range(w.n_steps):
+        for Q, ch, sh in gates:
+            S1, _ = itpp.normalize(itpp.apply_gate(S1, Q, ch, sh), n)
+        S1 = {P: c for P, c in S1.items() if P == ident or abs(c) > w.delta}
+
+    S2 = {ident: 1.0}
+    for _ in range(w.n_steps):
+        for Q, ch, sh in gates:
+            acc = {}
+            for P, c in S2.items():
+                for R, v in itpp.gate_contributions(P, c, Q, ch, sh):
+                    if abs(v) > w.delta:
+                        acc[R] = acc.get(R, 0.0) + v
+            S2, _ = itpp.normalize(itpp.truncate(acc, w.delta, w.K), n)
+
+    alg1, _ = itpp.run_workload(w)
+    for reading, ref in ((1, S1), (2, S2)):
+        o = c_oracle.COracle(w.n)
+        o.set_reading(reading)
+        o.evolve(w.strings, w.alphas, w.schedule, w.dtau, w.n_steps, w.delta, w.K)
+        assert o.state() == ref, reading
+        assert ref != alg1
+
+
 def test_sanitized_build_runs_clean(tmp_path):
     """The C++ oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
     (g++, host code only) runs every entry point on a small capped chain
