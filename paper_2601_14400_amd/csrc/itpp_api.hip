@@ -952,8 +952,8 @@ static itpp_status build_gate(itpp_ctx c, int i, const std::vector<int>& pos, do
 
 // Gate kernel shape of the next launches: the option, or the size rule of
 // kShapeAuto. With forward checkpoints the automatic choice is shape 1, the
-// layout the reverse sweep replays. The layer kernel has no weight cutoff, so
-// such gates run on shape 1.
+// shape the reverse sweep's recomputation is verified with. The layer kernel
+// has no weight cutoff, so such gates run on shape 1.
 static int effective_shape(itpp_ctx c) {
   int s = c->shape;
   if (s == kShapeAuto) s = (c->ckpt_every == 0 && c->state_hint <= kAutoShapeMaxStrings) ? 2 : 1;
