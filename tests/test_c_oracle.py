@@ -227,3 +227,24 @@ def test_sanitized_build_runs_clean(tmp_path):
     assert r.returncode == 0, r.stdout + r.stderr
     assert "0 failures" in r.stdout
     assert "runtime error" not in r.stderr and "ERROR: AddressSanitizer" not in r.stderr
+
+
+@pytest.mark.parametrize("precision,K", [("f64", 10 ** 6), ("f64", 120), ("f32", 200)])
+def test_twin_on_xxz_chain(precision, K):
+    """The C++ twin equals the Python oracle bit for bit on an XXZ chain (YY
+    terms flip four key bits), untruncated and with the cap binding."""
+    c_oracle.build(force=False)
+    n = 7
+    bonds = [(i, i + 1) for i in range(n - 1)]
+    strings, alphas = [], []
+    for letter, a in (("X", 0.8), ("Y", 0.8), ("Z", -0.5)):
+        for i, j in bonds:
+            s = ["I"] * n
+            s[i] = s[j] = letter
+            strings.append("".join(s))
+            alphas.append(a)
+    sched = [(k, 1.0) for k in range(len(strings))]
+    w = W.Workload("xxz", n, strings, alphas, sched, 0.05, 6, 1e-10, K, precision=precision)
+    S, _ = itpp.run_workload(w)
+    assert c_oracle.run_workload(w).state() == S
+    assert any("Y" in P for P in S)
