@@ -12,7 +12,9 @@ of beta = 2 tau, and prints the strings kept at the end and the energy error
 against the free-fermion ground state.
 
 Usage (from the repository root):
-    python tests/readings_report.py [cases as reading:angle_multiplier:exponent, e.g. 1:1:7]
+    python tests/readings_report.py [cases as reading:angle_multiplier:exponent[:order], e.g. 1:1:7]
+order (default 1): 1 = first order, ZZ gates then X gates; 3 = first order,
+X gates then ZZ gates; 2 = Strang (half ZZ, X, half ZZ).
 (no cases: every reading, both angles, thresholds 2^-6, 2^-7, 2^-8; the runs
 go to a process pool, one per core, and the table prints in case order).
 """
@@ -30,9 +32,12 @@ from oracle import freefermion as FF  # noqa: E402
 from oracle import itpp as OR  # noqa: E402
 
 
-def run(n, reading, delta, angle_mult, steps=500, dtau=0.04, J=1.0, h=0.5):
+def run(n, reading, delta, angle_mult, order=1, steps=500, dtau=0.04, J=1.0, h=0.5):
     strings, alphas, _ = W.tfim_terms(n, J, h, False)
-    sched = W.tfim_schedule(n - 1, n, 1)
+    if order == 3:
+        sched = [(k, 1.0) for k in range(n - 1, 2 * n - 1)] + [(k, 1.0) for k in range(n - 1)]
+    else:
+        sched = W.tfim_schedule(n - 1, n, order)
     o = c_oracle.COracle(n)
     o.set_reading(reading)
     t0 = time.perf_counter()
@@ -43,8 +48,8 @@ def run(n, reading, delta, angle_mult, steps=500, dtau=0.04, J=1.0, h=0.5):
 
 
 def one(case):
-    reading, mult, ex = case
-    cnt, e, dt = run(12, reading, 2.0 ** -ex, mult)
+    reading, mult, ex, order = case
+    cnt, e, dt = run(12, reading, 2.0 ** -ex, mult, order)
     return case, cnt, e, dt
 
 
@@ -54,20 +59,22 @@ def main():
     n = 12
     if len(sys.argv) > 1:
         cases = [tuple(int(v) if i != 1 else float(v) for i, v in enumerate(a.split(":"))) for a in sys.argv[1:]]
+        cases = [c + (1,) if len(c) == 3 else c for c in cases]
     else:
-        cases = [(r, m, ex) for r in (0, 1, 2) for m in (1.0, 2.0) for ex in (6, 7, 8)]
+        cases = [(r, m, ex, 1) for r in (0, 1, 2) for m in (1.0, 2.0) for ex in (6, 7, 8)]
     exact = FF.ground_energy(n, 1.0, 0.5, False) / n
     print(f"# Threshold readings, open TFIM N = {n}, J = 1, h = 0.5, dtau = 0.04, 500 steps\n")
     print("Command (repository root, CPU): `python tests/readings_report.py " + " ".join(sys.argv[1:]) + "`\n")
     print(f"Free-fermion ground-state energy per site: {exact:.10f}.  The paper quotes 42,466 strings at 2^-7.\n")
-    print("| reading | gate angle | threshold | strings at the end | energy per site | relative error | seconds |")
-    print("|---|---|---|---:|---:|---:|---:|")
+    print("| reading | gate order | gate angle | threshold | strings at the end | energy per site | relative error | seconds |")
+    print("|---|---|---|---|---:|---:|---:|---:|")
     names = {0: "after every gate (Algorithm 1)", 1: "once per Trotter step", 2: "every contribution, then sums"}
+    orders = {1: "ZZ then X", 3: "X then ZZ", 2: "Strang"}
     with ProcessPoolExecutor(max_workers=min(len(cases), os.cpu_count() or 1)) as ex:
-        for (reading, mult, e2), cnt, e, dt in ex.map(one, cases):
+        for (reading, mult, e2, order), cnt, e, dt in ex.map(one, cases):
             aname = "h dtau" if mult == 1.0 else f"{mult:g} h dtau"
-            print(f"| {names[reading]} | {aname} | 2^-{e2} | {cnt} | {e:.10f} | {abs(e - exact) / abs(exact):.3e} | {dt:.1f} |",
-                  flush=True)
+            print(f"| {names[reading]} | {orders[order]} | {aname} | 2^-{e2} | {cnt} | {e:.10f} | "
+                  f"{abs(e - exact) / abs(exact):.3e} | {dt:.1f} |", flush=True)
 
 
 if __name__ == "__main__":
