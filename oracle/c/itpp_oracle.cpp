@@ -87,7 +87,10 @@ struct Oracle {
   // 1 = threshold once per Trotter step, on the normalised state after its
   //     last gate (the gates of a step only propagate and normalise);
   // 2 = threshold every contribution of Eq. ITPP_PropRules before the
-  //     accumulation, then the sums as in Algorithm 1.
+  //     accumulation, then the sums as in Algorithm 1;
+  // 3 = as 1, on the step's coefficients before its normalisation: a string
+  //     is kept when |c| times the product of the identity coefficients its
+  //     gates divided by exceeds the threshold.
   int reading = 0;
 };
 
@@ -230,18 +233,22 @@ int evolve_impl(Oracle* o, int n_terms, const char* strings, const double* alpha
   const std::string ident(n, 'I');
   std::vector<std::string> terms(n_terms);
   for (int k = 0; k < n_terms; ++k) terms[k] = std::string(strings + (size_t)k * n, n);
-  const bool per_step = o->reading == 1;
+  const bool per_step = o->reading == 1 || o->reading == 3;
   for (long long step = 0; step < n_steps; ++step) {
+    double growth = 1.0;  // product of the step's identity coefficients before normalisation
     for (int g = 0; g < n_gates; ++g) {
       const std::string& Q = terms[term_idx[g]];
       if (Q == ident) continue;
       const double theta = alpha[term_idx[g]] * mult[g] * dtau;
-      const int rc = one_gate<T>(o, S, Q, theta, per_step ? -1.0 : delta, per_step ? (long long)1 << 62 : K, nullptr);
+      double bI = 1.0;
+      const int rc = one_gate<T>(o, S, Q, theta, per_step ? -1.0 : delta, per_step ? (long long)1 << 62 : K, &bI);
       if (rc) return rc;
+      growth *= bI;
     }
     if (per_step) {
+      const double scale = o->reading == 3 ? growth : 1.0;
       for (auto it = S.begin(); it != S.end();) {
-        if (it->first != ident && !((double)std::fabs(it->second) > delta)) it = S.erase(it);
+        if (it->first != ident && !((double)std::fabs(it->second) * scale > delta)) it = S.erase(it);
         else ++it;
       }
       if ((long long)S.size() > K) {

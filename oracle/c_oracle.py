@@ -97,7 +97,9 @@ class COracle:
 
     def set_reading(self, reading: int) -> None:
         """Where the threshold applies: 0 Algorithm 1 (after every gate),
-        1 once per Trotter step, 2 on every contribution before the sums."""
+        1 once per Trotter step, 2 on every contribution before the sums,
+        3 once per Trotter step on the coefficients before the step's
+        normalisation."""
         self._lib.itpp_oracle_set_reading(self._h, int(reading))
 
     def set_max_weight(self, max_weight: int) -> None:

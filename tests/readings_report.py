@@ -7,7 +7,8 @@ Algorithm 1 (threshold after every gate) keeps far fewer there.  This runs
 the oracle under the readings of where the threshold applies:
 0 = after every gate (Algorithm 1), 1 = once per Trotter step on the
 normalised state, 2 = on every contribution before the accumulation (then on
-the sums), each with the printed gate angle h dtau and with the doubled angle
+the sums), 3 = once per Trotter step on the coefficients before the step's
+normalisation, each with the printed gate angle h dtau and with the doubled angle
 of beta = 2 tau, and prints the strings kept at the end and the energy error
 against the free-fermion ground state.
 
@@ -68,7 +69,8 @@ def main():
     print(f"Free-fermion ground-state energy per site: {exact:.10f}.  The paper quotes 42,466 strings at 2^-7.\n")
     print("| reading | gate order | gate angle | threshold | strings at the end | energy per site | relative error | seconds |")
     print("|---|---|---|---|---:|---:|---:|---:|")
-    names = {0: "after every gate (Algorithm 1)", 1: "once per Trotter step", 2: "every contribution, then sums"}
+    names = {0: "after every gate (Algorithm 1)", 1: "once per Trotter step", 2: "every contribution, then sums",
+             3: "once per Trotter step, before normalising"}
     orders = {1: "ZZ then X", 3: "X then ZZ", 2: "Strang"}
     with ProcessPoolExecutor(max_workers=min(len(cases), os.cpu_count() or 1)) as ex:
         for (reading, mult, e2, order), cnt, e, dt in ex.map(one, cases):

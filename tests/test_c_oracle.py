@@ -174,7 +174,10 @@ def test_threshold_readings_match_their_definitions(n, periodic, order):
     1 = every gate only propagates and normalises, and the normalised state
         is thresholded once after the last gate of each Trotter step;
     2 = every contribution of Eq. ITPP_PropRules is thresholded before the
-        sums, then the gate truncates and normalises as in Algorithm 1."""
+        sums, then the gate truncates and normalises as in Algorithm 1;
+    3 = as 1, on the coefficients before the step's normalisation (the
+        normalised ones times the product of the step's identity
+        coefficients)."""
     c_oracle.build(force=False)
     w = W.tfim_workload("t", n, 1.0, 0.5, periodic, order, 0.04, 0.4, 2.0 ** -7, 10 ** 9)
     ident = "I" * n
@@ -197,8 +200,17 @@ def test_threshold_readings_match_their_definitions(n, periodic, order):
                         acc[R] = acc.get(R, 0.0) + v
             S2, _ = itpp.normalize(itpp.truncate(acc, w.delta, w.K), n)
 
+    S3 = {ident: 1.0}
+    for _ in range(w.n_steps):
+        growth = 1.0
+        for Q, ch, sh in gates:
+            S3, cI = itpp.normalize(itpp.apply_gate(S3, Q, ch, sh), n)
+            growth *= cI
+        S3 = {P: c for P, c in S3.items() if P == ident or abs(c) * growth > w.delta}
+
     alg1, _ = itpp.run_workload(w)
-    for reading, ref in ((1, S1), (2, S2)):
+    assert S3 != S1
+    for reading, ref in ((1, S1), (2, S2), (3, S3)):
         o = c_oracle.COracle(w.n)
         o.set_reading(reading)
         o.evolve(w.strings, w.alphas, w.schedule, w.dtau, w.n_steps, w.delta, w.K)
